@@ -1,0 +1,102 @@
+/* me.h -- C ABI of the MI355X leading-order matrix-element library (libme.so).
+ *
+ * The library computes, for every phase-space event independently, the tree-level
+ * matrix element of a fixed process, summed over helicities and colours and averaged
+ * over the initial states (the per-event ME calculation of the paper, Sec. 1 and 2; the
+ * process set ee->mumu, gg->tt~ + 0..3 gluons of Sec. 2).  The GPU path evaluates every
+ * Feynman diagram with HELAS-style wavefunctions, accumulates the colour-flow amplitudes,
+ * contracts them with the colour matrix on the matrix cores and sums the helicities that
+ * a pre-pass found to contribute.
+ *
+ * Conventions.  Units GeV; momenta (E, px, py, pz), metric (+,-,-,-).  Particle order:
+ *   ee_mumu  (e+, e-, mu+, mu-)
+ *   gg_tt    (g, g, t, t~)          gg_ttg  (g, g, t, t~, g)
+ *   gg_ttgg  (g, g, t, t~, g, g)    gg_ttggg (g, g, t, t~, g, g, g)
+ *   gg_gg    (g, g, g, g)           (test process)
+ * The returned value is the spin- and colour-averaged |M|^2 WITHOUT the identical-
+ * particle factor (me_info reports that factor as sym_factor).
+ *
+ * Memory.  Event buffers are DEVICE memory owned by the caller and must stay alive until
+ * the work enqueued on `stream` has completed.  `stream` is a hipStream_t (NULL: the null
+ * stream).  Calls enqueue work and return without synchronising, except me_create, which
+ * runs the helicity pre-pass and synchronises on `stream` once.
+ *
+ * Errors.  Functions return ME_OK (0) or a negative code; me_create returns NULL on
+ * error.  me_last_error() gives a message for the calling thread's last error.  No
+ * exception crosses the ABI.  HIP errors of asynchronous work surface at a later call.
+ */
+#ifndef ME_H
+#define ME_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ME_FP64 = 0, ME_MIXED_FP16 = 1 };
+enum { ME_OK = 0, ME_EINVAL = -1, ME_ENOPROC = -2, ME_ENOMEM = -3, ME_EHIP = -4 };
+
+typedef struct me_handle me_handle; /* opaque, owned by the library */
+
+/* Create a handle for `process` (see the list above).
+ * masses:    {m_t} or {m_t, w_t}; the top width must be 0 (no width in propagators).
+ *            Ignored by ee_mumu and gg_gg.  NULL: m_t = 173.
+ * couplings: {alpha_em, alpha_s}; NULL: {1/132.507, 0.118}.  Fixed couplings.
+ * precision: ME_FP64 (all FP64) or ME_MIXED_FP16 (FP32 wavefunctions and amplitudes,
+ *            FP16 matrix-core colour sum with FP32 accumulation, FP64 momenta,
+ *            propagator denominators and helicity sum).
+ * Copies the arrays, uploads the colour matrix and helicity table, and runs the
+ * helicity-filter pre-pass: 1024 RAMBO events from the fixed seed 0x5EED, every helicity
+ * evaluated, helicity h kept iff max_e |M_h(e)|^2 / |M(e)|^2 > 1e-20.  The mask does not
+ * depend on later inputs.  Returns NULL on error. */
+me_handle *me_create(const char *process, const double *masses, int n_masses,
+                     const double *couplings, int n_couplings, int precision, void *stream);
+
+/* RAMBO phase-space points for the handle's process at energy sqrt_s:
+ * out = DEVICE double[n_evt][n_par][4], events evt0 .. evt0+n_evt-1 of the stream `seed`
+ * (Philox4x64-10, key (seed, 0), counter (event * n_final + particle, 0, 0, 0)).  Beams are
+ * particles 0 and 1 along +z and -z.  n_evt == 0 is a no-op.  ME_EINVAL for a NULL or host
+ * pointer, n_evt < 0, evt0 < 0, or sqrt_s not above the sum of final-state masses. */
+int rambo_momenta(const me_handle *h, uint64_t seed, double sqrt_s, int64_t evt0, int64_t n_evt,
+                  double *out, void *stream);
+
+/* out_me2[e] = averaged |M|^2 of event e for momenta = DEVICE double[n_evt][n_par][4]
+ * (16-byte aligned).  n_evt == 0 is a no-op.  ME_EINVAL for NULL or host pointers,
+ * misalignment or n_evt < 0.  Unphysical momenta are not checked (they give NaN/inf).
+ * Work is split into chunks that bound the handle's per-stream scratch; calls on
+ * different streams may overlap. */
+int me_sigma(me_handle *h, const double *momenta, int64_t n_evt, double *out_me2, void *stream);
+
+/* As me_sigma, and also out_hel[e * n_good + k] = colour-summed |M_h|^2 (not averaged) of
+ * the k-th good helicity of event e (DEVICE double[n_evt][n_good], may be NULL). */
+int me_sigma_hel(me_handle *h, const double *momenta, int64_t n_evt, double *out_me2, double *out_hel,
+                 void *stream);
+
+typedef struct {
+    int n_par, n_diagrams, n_amplitudes, n_colors, n_hel, n_good_hel, precision;
+    double avg_factor, sym_factor;
+    double flops_amp_lane;     /* algorithmic flops of the amplitude kernel per (event, helicity) */
+    double flops_colour_lane;  /* algorithmic flops of the colour sum per (event, helicity) */
+    int64_t bytes_resident;    /* device bytes held by the handle (tables) */
+    int64_t bytes_per_event_scratch; /* jamp scratch per event (per stream in use) */
+    int64_t chunk_events;      /* events per amplitude/colour-sum launch pair */
+} me_info_t;
+
+int me_info(const me_handle *h, me_info_t *out);
+
+/* good helicities: out[k * n_par + i] = helicity (+1/-1) of particle i in the k-th good
+ * combination; out must hold n_good_hel * n_par bytes.  Returns n_good_hel. */
+int me_good_helicities(const me_handle *h, signed char *out);
+
+/* the pre-pass statistic: out[hh] = max over its events of |M_hh|^2 / |M|^2, for all
+ * n_hel helicity combinations (index: particle i's bit (l+1)/2 at 2^(n_par-1-i)). */
+int me_helicity_ratios(const me_handle *h, double *out);
+
+const char *me_last_error(void); /* thread-local; valid until the thread's next call */
+
+void me_destroy(me_handle *h); /* frees the handle and its device memory; NULL-safe */
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,147 @@
+"""Thin ctypes binding of libme.so (include/me.h): argument marshalling only.
+
+Every step of the matrix-element path runs in the HIP kernels of libme.so; torch is used
+for device memory and streams.  Loading fails loudly if the library was not built -- there
+is no fallback.
+"""
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libme.so")
+
+ME_FP64, ME_MIXED_FP16 = 0, 1
+PRECISIONS = {"fp64": ME_FP64, "mixed_fp16": ME_MIXED_FP16}
+ME_OK = 0
+PROCESSES = ["ee_mumu", "gg_tt", "gg_ttg", "gg_ttgg", "gg_ttggg", "gg_gg"]
+
+
+class MeError(RuntimeError):
+    pass
+
+
+class MeInfo(ctypes.Structure):
+    _fields_ = [("n_par", ctypes.c_int), ("n_diagrams", ctypes.c_int), ("n_amplitudes", ctypes.c_int),
+                ("n_colors", ctypes.c_int), ("n_hel", ctypes.c_int), ("n_good_hel", ctypes.c_int),
+                ("precision", ctypes.c_int), ("avg_factor", ctypes.c_double), ("sym_factor", ctypes.c_double),
+                ("flops_amp_lane", ctypes.c_double), ("flops_colour_lane", ctypes.c_double),
+                ("bytes_resident", ctypes.c_int64), ("bytes_per_event_scratch", ctypes.c_int64),
+                ("chunk_events", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+EXPORTS = ["me_create", "me_destroy", "me_info", "me_last_error", "rambo_momenta", "me_sigma",
+           "me_sigma_hel", "me_good_helicities", "me_helicity_ratios"]
+
+_lib = None
+
+
+def load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise MeError(f"{LIB_PATH} is not built: run __graft_entry__.build() (hipcc for gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, D = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+    L.me_create.restype = vp
+    L.me_create.argtypes = [ctypes.c_char_p, D, ctypes.c_int, D, ctypes.c_int, ctypes.c_int, vp]
+    L.me_destroy.argtypes = [vp]
+    L.me_destroy.restype = None
+    L.me_info.argtypes = [vp, ctypes.POINTER(MeInfo)]
+    L.me_last_error.restype = ctypes.c_char_p
+    L.rambo_momenta.argtypes = [vp, ctypes.c_uint64, ctypes.c_double, ctypes.c_int64, ctypes.c_int64, vp, vp]
+    L.me_sigma.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
+    L.me_sigma_hel.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp]
+    L.me_good_helicities.argtypes = [vp, ctypes.POINTER(ctypes.c_byte)]
+    L.me_helicity_ratios.argtypes = [vp, D]
+    _lib = L
+    return L
+
+
+def last_error():
+    return load().me_last_error().decode()
+
+
+def _check(rc, what):
+    if rc != ME_OK:
+        raise MeError(f"{what} failed ({rc}): {last_error()}")
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Process:
+    """One process handle: ``rambo`` makes device momenta, ``sigma`` the averaged |M|^2."""
+
+    def __init__(self, name, m_top=173.0, alpha_em=1.0 / 132.507, alpha_s=0.118, precision="fp64",
+                 stream=None):
+        L = load()
+        self.name = name
+        masses = (ctypes.c_double * 1)(m_top)
+        coup = (ctypes.c_double * 2)(alpha_em, alpha_s)
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        h = L.me_create(name.encode(), masses, 1, coup, 2, prec, _stream_ptr(stream))
+        if not h:
+            raise MeError(f"me_create({name}) failed: {last_error()}")
+        self._h = ctypes.c_void_p(h)
+        self.info = self._info()
+        self.n_par = self.info["n_par"]
+
+    def _info(self):
+        i = MeInfo()
+        _check(load().me_info(self._h, ctypes.byref(i)), "me_info")
+        return i.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().me_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def rambo(self, seed, sqrt_s, n_evt, evt0=0, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty((n_evt, self.n_par, 4), dtype=torch.float64, device="cuda")
+        _check(load().rambo_momenta(self._h, seed, sqrt_s, evt0, n_evt, ctypes.c_void_p(out.data_ptr()),
+                                    _stream_ptr(stream)), "rambo_momenta")
+        return out
+
+    def sigma(self, momenta, out=None, per_helicity=False, stream=None):
+        import torch
+        assert momenta.is_cuda and momenta.dtype == torch.float64 and momenta.is_contiguous()
+        n = momenta.shape[0]
+        assert momenta.shape[1:] == (self.n_par, 4)
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=momenta.device)
+        if per_helicity:
+            hel = torch.empty((n, self.info["n_good_hel"]), dtype=torch.float64, device=momenta.device)
+            _check(load().me_sigma_hel(self._h, ctypes.c_void_p(momenta.data_ptr()), n,
+                                       ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(hel.data_ptr()),
+                                       _stream_ptr(stream)), "me_sigma_hel")
+            return out, hel
+        _check(load().me_sigma(self._h, ctypes.c_void_p(momenta.data_ptr()), n, ctypes.c_void_p(out.data_ptr()),
+                               _stream_ptr(stream)), "me_sigma")
+        return out
+
+    def good_helicities(self):
+        n = self.info["n_good_hel"]
+        buf = (ctypes.c_byte * (n * self.n_par))()
+        load().me_good_helicities(self._h, buf)
+        return [tuple(buf[k * self.n_par:(k + 1) * self.n_par]) for k in range(n)]
+
+    def helicity_ratios(self):
+        n = self.info["n_hel"]
+        buf = (ctypes.c_double * n)()
+        load().me_helicity_ratios(self._h, buf)
+        return list(buf)

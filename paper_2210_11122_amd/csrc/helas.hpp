@@ -1,0 +1,401 @@
+// helas.hpp -- per-lane wavefunction algebra for the tree-level matrix-element kernels.
+//
+// One lane holds one (event, helicity) pair.  Wavefunctions are four complex components
+// (a Dirac spinor in the chiral representation, or a contravariant Lorentz vector) in the
+// real type R: double for the FP64 kernels, float for the mixed-precision kernels.
+// Momenta, propagator denominators and momentum sums are always double; in the mixed form
+// they are rounded to float only where they multiply a wavefunction.
+//
+// Conventions (the standard LO Feynman rules in Feynman gauge, metric (+,-,-,-)):
+//   quark-gluon vertex  i g gamma^mu (colour t^a stripped)
+//   quark propagator    i (qslash + m) / (q^2 - m^2)
+//   gluon propagator    -i g_{mu nu} / P^2
+//   three-gluon vertex  g [g^{mu nu}(k-p)^rho + g^{nu rho}(p-q)^mu + g^{rho mu}(q-k)^nu]
+//                       (colour f^{abc} stripped, all momenta incoming)
+//   four-gluon vertex   -i g^2 x (one of its three Lorentz structures; colour f f stripped)
+// External states are helicity eigenstates with the HELAS phase conventions (Hagiwara,
+// Murayama, Watanabe, KEK-91-11): u(p,l) = (w_{-l} chi_l, w_l chi_l),
+// v(p,l) = (-l w_l chi_{-l}, l w_{-l} chi_{-l}), w_pm = sqrt(E pm |p|), and
+// eps(k,l) = (-l e1 - i e2)/sqrt(2) (complex conjugate for an outgoing gluon).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace me {
+
+template <class R>
+struct cx {
+    R r, i;
+};
+
+template <class R>
+__device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.r + b.r, a.i + b.i}; }
+template <class R>
+__device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.r - b.r, a.i - b.i}; }
+template <class R>
+__device__ __forceinline__ cx<R> operator*(cx<R> a, cx<R> b)
+{
+    return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r};
+}
+template <class R>
+__device__ __forceinline__ cx<R> operator*(R s, cx<R> a) { return {s * a.r, s * a.i}; }
+// i * a
+template <class R>
+__device__ __forceinline__ cx<R> mul_i(cx<R> a) { return {-a.i, a.r}; }
+
+struct P4 {
+    double t, x, y, z;
+};
+__device__ __forceinline__ P4 operator+(const P4& a, const P4& b)
+{
+    return {a.t + b.t, a.x + b.x, a.y + b.y, a.z + b.z};
+}
+__device__ __forceinline__ P4 operator-(const P4& a, const P4& b)
+{
+    return {a.t - b.t, a.x - b.x, a.y - b.y, a.z - b.z};
+}
+__device__ __forceinline__ P4 operator-(const P4& a) { return {-a.t, -a.x, -a.y, -a.z}; }
+__device__ __forceinline__ double msq(const P4& a) { return a.t * a.t - a.x * a.x - a.y * a.y - a.z * a.z; }
+
+template <class R>
+struct W4 {
+    cx<R> c[4];
+};
+
+// Minkowski product of two complex vectors (no conjugation)
+template <class R>
+__device__ __forceinline__ cx<R> dot(const W4<R>& a, const W4<R>& b)
+{
+    return a.c[0] * b.c[0] - a.c[1] * b.c[1] - a.c[2] * b.c[2] - a.c[3] * b.c[3];
+}
+// real vector in the working precision
+template <class R>
+struct R4 {
+    R t, x, y, z;
+};
+template <class R>
+__device__ __forceinline__ R4<R> rnd(const P4& p) { return {(R)p.t, (R)p.x, (R)p.y, (R)p.z}; }
+template <class R>
+__device__ __forceinline__ cx<R> dot(const W4<R>& a, const R4<R>& k)
+{
+    return {a.c[0].r * k.t - a.c[1].r * k.x - a.c[2].r * k.y - a.c[3].r * k.z,
+            a.c[0].i * k.t - a.c[1].i * k.x - a.c[2].i * k.y - a.c[3].i * k.z};
+}
+
+// ------------------------------------------------------------------------------------
+// external states (computed in double, rounded to R)
+
+// two-component helicity eigenstates of sigma.p/|p|; (0,1) / (-1,0) for p along -z
+__device__ __forceinline__ void chi2(const P4& p, int lam, double out[4])
+{
+    double pp = sqrt(p.x * p.x + p.y * p.y + p.z * p.z);
+    double d = (p.z >= 0.0) ? pp + p.z : (p.x * p.x + p.y * p.y) / (pp - p.z);
+    if (!(d > 0.0)) {
+        if (lam > 0) { out[0] = 0; out[1] = 0; out[2] = 1; out[3] = 0; }
+        else { out[0] = -1; out[1] = 0; out[2] = 0; out[3] = 0; }
+        return;
+    }
+    double nrm = 1.0 / sqrt(2.0 * pp * d);
+    if (lam > 0) { out[0] = d * nrm; out[1] = 0; out[2] = p.x * nrm; out[3] = p.y * nrm; }
+    else { out[0] = -p.x * nrm; out[1] = p.y * nrm; out[2] = d * nrm; out[3] = 0; }
+}
+
+// u(p, lam) as a row ubar = u^dagger gamma^0 = (u2*, u3*, u0*, u1*)
+template <class R>
+__device__ __forceinline__ W4<R> ext_ubar(const P4& p, double m, int lam)
+{
+    double c[4];
+    chi2(p, lam, c);
+    double wp = sqrt(p.t + sqrt(p.x * p.x + p.y * p.y + p.z * p.z));
+    double wm = (m == 0.0) ? 0.0 : m / wp;
+    double up = lam > 0 ? wm : wp, lo = lam > 0 ? wp : wm;
+    W4<R> w;
+    w.c[0] = {(R)(lo * c[0]), (R)(-lo * c[1])};
+    w.c[1] = {(R)(lo * c[2]), (R)(-lo * c[3])};
+    w.c[2] = {(R)(up * c[0]), (R)(-up * c[1])};
+    w.c[3] = {(R)(up * c[2]), (R)(-up * c[3])};
+    return w;
+}
+// u(p, lam) as a column
+template <class R>
+__device__ __forceinline__ W4<R> ext_u(const P4& p, double m, int lam)
+{
+    double c[4];
+    chi2(p, lam, c);
+    double wp = sqrt(p.t + sqrt(p.x * p.x + p.y * p.y + p.z * p.z));
+    double wm = (m == 0.0) ? 0.0 : m / wp;
+    double up = lam > 0 ? wm : wp, lo = lam > 0 ? wp : wm;
+    W4<R> w;
+    w.c[0] = {(R)(up * c[0]), (R)(up * c[1])};
+    w.c[1] = {(R)(up * c[2]), (R)(up * c[3])};
+    w.c[2] = {(R)(lo * c[0]), (R)(lo * c[1])};
+    w.c[3] = {(R)(lo * c[2]), (R)(lo * c[3])};
+    return w;
+}
+// v(p, lam) as a column
+template <class R>
+__device__ __forceinline__ W4<R> ext_v(const P4& p, double m, int lam)
+{
+    double c[4];
+    chi2(p, -lam, c);
+    double wp = sqrt(p.t + sqrt(p.x * p.x + p.y * p.y + p.z * p.z));
+    double wm = (m == 0.0) ? 0.0 : m / wp;
+    double wl = lam > 0 ? wp : wm, wml = lam > 0 ? wm : wp;
+    double up = -lam * wl, lo = lam * wml;
+    W4<R> w;
+    w.c[0] = {(R)(up * c[0]), (R)(up * c[1])};
+    w.c[1] = {(R)(up * c[2]), (R)(up * c[3])};
+    w.c[2] = {(R)(lo * c[0]), (R)(lo * c[1])};
+    w.c[3] = {(R)(lo * c[2]), (R)(lo * c[3])};
+    return w;
+}
+// v(p, lam) as a row vbar = v^dagger gamma^0
+template <class R>
+__device__ __forceinline__ W4<R> ext_vbar(const P4& p, double m, int lam)
+{
+    W4<R> v = ext_v<R>(p, m, lam);
+    W4<R> w;
+    w.c[0] = {v.c[2].r, -v.c[2].i};
+    w.c[1] = {v.c[3].r, -v.c[3].i};
+    w.c[2] = {v.c[0].r, -v.c[0].i};
+    w.c[3] = {v.c[1].r, -v.c[1].i};
+    return w;
+}
+// gluon / photon polarisation vector of momentum k; complex conjugate if outgoing
+template <class R>
+__device__ __forceinline__ W4<R> ext_vec(const P4& k, int lam, bool outgoing)
+{
+    double kt = sqrt(k.x * k.x + k.y * k.y);
+    double kk = sqrt(kt * kt + k.z * k.z);
+    double ct = k.z / kk, st = kt / kk, cp = 1.0, sp = 0.0;
+    if (kt > 0.0) { cp = k.x / kt; sp = k.y / kt; }
+    const double r = 0.70710678118654752440;
+    const double s = outgoing ? -r : r;
+    W4<R> w;
+    w.c[0] = {(R)0, (R)0};
+    w.c[1] = {(R)(-lam * r * ct * cp), (R)(s * sp)};
+    w.c[2] = {(R)(-lam * r * ct * sp), (R)(-s * cp)};
+    w.c[3] = {(R)(lam * r * st), (R)0};
+    return w;
+}
+
+// ------------------------------------------------------------------------------------
+// Dirac algebra in the chiral representation, gamma.G = [[0, G.sigma], [G.sigmabar, 0]]
+// with a = G0+G3, b = G0-G3, c = G1+iG2, d = G1-iG2.
+
+// (gamma.G) psi for a column spinor
+template <class R>
+__device__ __forceinline__ W4<R> gslash_col(const W4<R>& G, const W4<R>& s)
+{
+    cx<R> a = G.c[0] + G.c[3], b = G.c[0] - G.c[3];
+    cx<R> c = G.c[1] + mul_i(G.c[2]), d = G.c[1] - mul_i(G.c[2]);
+    W4<R> o;
+    o.c[0] = b * s.c[2] - d * s.c[3];
+    o.c[1] = a * s.c[3] - c * s.c[2];
+    o.c[2] = a * s.c[0] + d * s.c[1];
+    o.c[3] = c * s.c[0] + b * s.c[1];
+    return o;
+}
+// ubar (gamma.G) for a row spinor
+template <class R>
+__device__ __forceinline__ W4<R> gslash_row(const W4<R>& u, const W4<R>& G)
+{
+    cx<R> a = G.c[0] + G.c[3], b = G.c[0] - G.c[3];
+    cx<R> c = G.c[1] + mul_i(G.c[2]), d = G.c[1] - mul_i(G.c[2]);
+    W4<R> o;
+    o.c[0] = u.c[2] * a + u.c[3] * c;
+    o.c[1] = u.c[2] * d + u.c[3] * b;
+    o.c[2] = u.c[0] * b - u.c[1] * c;
+    o.c[3] = u.c[1] * a - u.c[0] * d;
+    return o;
+}
+// f (qslash + m) phi for a column spinor and real q
+template <class R>
+__device__ __forceinline__ W4<R> qslash_col(const R4<R>& q, R m, R f, const W4<R>& s)
+{
+    R a = q.t + q.z, b = q.t - q.z;
+    W4<R> o;
+    // c = q1 + i q2, d = q1 - i q2 (complex with real parts)
+    cx<R> cs2 = {q.x * s.c[2].r - q.y * s.c[2].i, q.x * s.c[2].i + q.y * s.c[2].r};  // c*s2
+    cx<R> ds3 = {q.x * s.c[3].r + q.y * s.c[3].i, q.x * s.c[3].i - q.y * s.c[3].r};  // d*s3
+    cx<R> cs0 = {q.x * s.c[0].r - q.y * s.c[0].i, q.x * s.c[0].i + q.y * s.c[0].r};  // c*s0
+    cx<R> ds1 = {q.x * s.c[1].r + q.y * s.c[1].i, q.x * s.c[1].i - q.y * s.c[1].r};  // d*s1
+    o.c[0] = f * (b * s.c[2] - ds3 + m * s.c[0]);
+    o.c[1] = f * (a * s.c[3] - cs2 + m * s.c[1]);
+    o.c[2] = f * (a * s.c[0] + ds1 + m * s.c[2]);
+    o.c[3] = f * (cs0 + b * s.c[1] + m * s.c[3]);
+    return o;
+}
+// f phibar (qslash + m) for a row spinor and real q
+template <class R>
+__device__ __forceinline__ W4<R> qslash_row(const R4<R>& q, R m, R f, const W4<R>& u)
+{
+    R a = q.t + q.z, b = q.t - q.z;
+    cx<R> u3c = {q.x * u.c[3].r - q.y * u.c[3].i, q.x * u.c[3].i + q.y * u.c[3].r};  // u3*c
+    cx<R> u2d = {q.x * u.c[2].r + q.y * u.c[2].i, q.x * u.c[2].i - q.y * u.c[2].r};  // u2*d
+    cx<R> u1c = {q.x * u.c[1].r - q.y * u.c[1].i, q.x * u.c[1].i + q.y * u.c[1].r};  // u1*c
+    cx<R> u0d = {q.x * u.c[0].r + q.y * u.c[0].i, q.x * u.c[0].i - q.y * u.c[0].r};  // u0*d
+    W4<R> o;
+    o.c[0] = f * (a * u.c[2] + u3c + m * u.c[0]);
+    o.c[1] = f * (u2d + b * u.c[3] + m * u.c[1]);
+    o.c[2] = f * (b * u.c[0] - u1c + m * u.c[2]);
+    o.c[3] = f * (a * u.c[1] - u0d + m * u.c[3]);
+    return o;
+}
+
+// ------------------------------------------------------------------------------------
+// currents and amplitudes
+
+// antiquark-side string extended by one vertex: S(q) (i g gamma.G) psi
+//   = -g/(q^2-m^2) (qslash + m)(gamma.G) psi
+template <class R>
+__device__ __forceinline__ W4<R> fstr_v(const W4<R>& psi, const W4<R>& G, const P4& q, double m, double g)
+{
+    double f = -g / (msq(q) - m * m);
+    return qslash_col<R>(rnd<R>(q), (R)m, (R)f, gslash_col<R>(G, psi));
+}
+// quark-side string extended by one vertex: ubar (i g gamma.G) S(q)
+template <class R>
+__device__ __forceinline__ W4<R> fstr_u(const W4<R>& ub, const W4<R>& G, const P4& q, double m, double g)
+{
+    double f = -g / (msq(q) - m * m);
+    return qslash_row<R>(rnd<R>(q), (R)m, (R)f, gslash_row<R>(ub, G));
+}
+// gluon emitted by the pair (ubar, psi): (-i/P^2)(i g ubar gamma^mu psi) = (g/P^2) ubar gamma^mu psi
+template <class R>
+__device__ __forceinline__ W4<R> jf(const W4<R>& u, const W4<R>& s, const P4& P, double g)
+{
+    R f = (R)(g / msq(P));
+    cx<R> u0s2 = u.c[0] * s.c[2], u1s3 = u.c[1] * s.c[3], u2s0 = u.c[2] * s.c[0], u3s1 = u.c[3] * s.c[1];
+    cx<R> u0s3 = u.c[0] * s.c[3], u1s2 = u.c[1] * s.c[2], u2s1 = u.c[2] * s.c[1], u3s0 = u.c[3] * s.c[0];
+    W4<R> o;
+    o.c[0] = f * (u0s2 + u1s3 + u2s0 + u3s1);
+    o.c[1] = f * (u0s3 + u1s2 - u2s1 - u3s0);
+    o.c[2] = f * mul_i(u1s2 - u0s3 + u2s1 - u3s0);
+    o.c[3] = f * (u0s2 - u1s3 - u2s0 + u3s1);
+    return o;
+}
+// three-gluon current with the off-shell leg first: (-i g / P^2) V, P = k1 + k2,
+// V = (J1.J2)(k1-k2) + J2 (J1.(k1+2k2)) - J1 (J2.(2k1+k2))
+template <class R>
+__device__ __forceinline__ W4<R> vvv_cur(const W4<R>& J1, const P4& k1, const W4<R>& J2, const P4& k2, double g)
+{
+    double f = g / msq(k1 + k2);
+    R4<R> a = rnd<R>(k1 - k2), b = rnd<R>(k1 + k2 + k2), c = rnd<R>(k1 + k1 + k2);
+    cx<R> d12 = dot(J1, J2), d1b = dot(J1, b), d2c = dot(J2, c);
+    R ar[4] = {a.t, a.x, a.y, a.z};
+    W4<R> o;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        cx<R> v = ar[mu] * d12 + J2.c[mu] * d1b - J1.c[mu] * d2c;
+        o.c[mu] = {(R)f * v.i, -(R)f * v.r};  // -i f v
+    }
+    return o;
+}
+// four-gluon current: (-i/P^2)(-i g^2) L = -(g^2/P^2) L with L one of
+//   S0: Jb (Ja.Jc) - Jc (Ja.Jb);  S1: Ja (Jb.Jc) - Jc (Ja.Jb);  S2: Ja (Jb.Jc) - Jb (Ja.Jc)
+template <class R, int S>
+__device__ __forceinline__ W4<R> vvvv_cur(const W4<R>& Ja, const W4<R>& Jb, const W4<R>& Jc, const P4& P, double g)
+{
+    R f = (R)(-g * g / msq(P));
+    W4<R> o;
+    if (S == 0) {
+        cx<R> ac = dot(Ja, Jc), ab = dot(Ja, Jb);
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) o.c[mu] = f * (Jb.c[mu] * ac - Jc.c[mu] * ab);
+    } else if (S == 1) {
+        cx<R> bc = dot(Jb, Jc), ab = dot(Ja, Jb);
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) o.c[mu] = f * (Ja.c[mu] * bc - Jc.c[mu] * ab);
+    } else {
+        cx<R> bc = dot(Jb, Jc), ac = dot(Ja, Jc);
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) o.c[mu] = f * (Ja.c[mu] * bc - Jb.c[mu] * ac);
+    }
+    return o;
+}
+// amplitude of a quark-gluon vertex: ubar (i g gamma.G) psi
+template <class R>
+__device__ __forceinline__ cx<R> amp_ffv(const W4<R>& u, const W4<R>& s, const W4<R>& G, double g)
+{
+    W4<R> t = gslash_col<R>(G, s);
+    cx<R> x = u.c[0] * t.c[0] + u.c[1] * t.c[1] + u.c[2] * t.c[2] + u.c[3] * t.c[3];
+    return (R)g * mul_i(x);
+}
+// amplitude of a three-gluon vertex with legs (x, a, b), incoming momenta kx, ka, kb:
+// g [(Wx.Wa)((kx-ka).Wb) + (Wa.Wb)((ka-kb).Wx) + (Wb.Wx)((kb-kx).Wa)]
+template <class R>
+__device__ __forceinline__ cx<R> amp_vvv(const W4<R>& Wx, const P4& kx, const W4<R>& Wa, const P4& ka,
+                                         const W4<R>& Wb, const P4& kb, double g)
+{
+    cx<R> xa = dot(Wx, Wa), ab = dot(Wa, Wb), bx = dot(Wb, Wx);
+    cx<R> t1 = dot(Wb, rnd<R>(kx - ka)), t2 = dot(Wx, rnd<R>(ka - kb)), t3 = dot(Wa, rnd<R>(kb - kx));
+    return (R)g * (xa * t1 + ab * t2 + bx * t3);
+}
+// amplitude of a four-gluon vertex, legs (x, a, b, c): -i g^2 times
+//   S0: (x.b)(a.c) - (x.c)(a.b);  S1: (x.a)(b.c) - (x.c)(a.b);  S2: (x.a)(b.c) - (x.b)(a.c)
+template <class R, int S>
+__device__ __forceinline__ cx<R> amp_vvvv(const W4<R>& Wx, const W4<R>& Wa, const W4<R>& Wb, const W4<R>& Wc,
+                                          double g)
+{
+    cx<R> v;
+    if (S == 0) v = dot(Wx, Wb) * dot(Wa, Wc) - dot(Wx, Wc) * dot(Wa, Wb);
+    else if (S == 1) v = dot(Wx, Wa) * dot(Wb, Wc) - dot(Wx, Wc) * dot(Wa, Wb);
+    else v = dot(Wx, Wa) * dot(Wb, Wc) - dot(Wx, Wb) * dot(Wa, Wc);
+    cx<R> iv = mul_i(v);
+    return (R)(-g * g) * iv;
+}
+
+// ------------------------------------------------------------------------------------
+// launch helpers
+
+// Workgroups are dealt to the 8 XCDs round-robin; renumber them so that consecutive
+// logical workgroup ids (the helicities of one event block) share an XCD and its L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t w, int64_t n)
+{
+    const int64_t nx = 8;
+    int64_t xcd = w % nx, idx = w / nx;
+    int64_t per = n / nx, rem = n % nx;
+    return (xcd < rem) ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+// Stage the momenta of events [e0, e0+64) (layout [event][particle][4], double) through
+// LDS with coalesced 16-byte loads, into lds[component][lane]; lanes past n_evt read zeros.
+template <int NPAR>
+__device__ __forceinline__ void stage_momenta(const double* __restrict__ mom, int64_t n_evt, int64_t e0,
+                                              double* lds, int lane)
+{
+    constexpr int NCOMP = 4 * NPAR;
+    const double2* src = reinterpret_cast<const double2*>(mom + e0 * NCOMP);
+    const int64_t n_here = (n_evt - e0) < 64 ? (n_evt - e0) : 64;
+#pragma unroll
+    for (int k = 0; k < NCOMP / 2; ++k) {
+        int f = lane + 64 * k;        // double2 index within the block
+        int ev = (2 * f) / NCOMP;     // event within the block
+        int c = (2 * f) % NCOMP;      // first component
+        double2 v = {0.0, 0.0};
+        if (ev < n_here) v = src[f];
+        lds[c * 64 + ev] = v.x;
+        lds[(c + 1) * 64 + ev] = v.y;
+    }
+    __syncthreads();
+}
+
+}  // namespace me
+
+namespace me {
+// momentum of particle i of this lane's event, re-read from the LDS staging area at every
+// use (volatile: the compiler neither caches nor hoists it, so no four-momentum stays live)
+__device__ __forceinline__ P4 lds_p4(const double* lds, int i, int lane)
+{
+    const volatile double* v = lds;
+    return {v[(4 * i) * 64 + lane], v[(4 * i + 1) * 64 + lane], v[(4 * i + 2) * 64 + lane],
+            v[(4 * i + 3) * 64 + lane]};
+}
+// LDS atomic add into this lane's private jamp slot (no return value: ds_add_f64 / ds_add_f32)
+template <class R>
+__device__ __forceinline__ void lds_add(R* p, R v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+}  // namespace me

@@ -1,0 +1,426 @@
+// me_abi.cpp -- the C ABI of libme.so (declared in include/me.h).
+//
+// A handle owns the resident tables of one process: the colour matrix as matrix-core
+// operands, the list of helicities that contribute, and one jamp scratch buffer per
+// stream.  me_sigma runs, chunk by chunk, the generated amplitude kernel (one lane per
+// (event, helicity)) and the colour-sum kernel (matrix cores, helicity sum in FP64).
+#include "me.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "colorsum.hpp"
+#include "process.hpp"
+#include "rambo.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+const me::ProcessDesc* find_process(const char* name)
+{
+    const me::ProcessDesc* all[] = {me::process_ee_mumu(), me::process_gg_tt(),   me::process_gg_ttg(),
+                                    me::process_gg_ttgg(), me::process_gg_ttggg(), me::process_gg_gg()};
+    for (auto* p : all)
+        if (p && std::strcmp(p->name, name) == 0) return p;
+    return nullptr;
+}
+
+struct Scratch {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+constexpr double PI = 3.141592653589793238462643383279502884;
+constexpr size_t SCRATCH_CAP = size_t(1) << 30;  // jamp scratch per stream
+constexpr int PREPASS_EVENTS = 1024;
+constexpr uint64_t PREPASS_SEED = 0x5EED;
+constexpr double PREPASS_THRESHOLD = 1e-20;
+
+bool is_device_pointer(const void* p)
+{
+    if (!p) return false;
+    hipPointerAttribute_t a;
+    hipError_t e = hipPointerGetAttributes(&a, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+}  // namespace
+
+struct me_handle {
+    const me::ProcessDesc* P = nullptr;
+    int precision = ME_FP64;
+    double mt = 173.0, alpha_em = 1.0 / 132.507, alpha_s = 0.118, g = 0.0;
+    int n_good = 0;
+    signed char* d_hel_good = nullptr;
+    std::vector<signed char> h_hel_good;
+    std::vector<double> hel_ratio;
+    double* d_aop64 = nullptr;
+    _Float16* d_aop16 = nullptr;
+    size_t bytes_resident = 0;
+    int64_t chunk = 0;
+    size_t bytes_per_event = 0;
+    std::mutex mu;
+    std::unordered_map<hipStream_t, Scratch> scratch;
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------------------
+// kernel dispatch over the compile-time colour-flow count
+
+template <int NC>
+hipError_t launch_cs64(const double* J, int64_t ld, int n_good, int64_t n, const double* aop, double sh, double sa,
+                       double* out, double* out_hel, hipStream_t st)
+{
+    hipLaunchKernelGGL(me::colour_sum_f64<NC>, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, st, J, ld, n_good, n,
+                       aop, sh, sa, out, out_hel);
+    return hipGetLastError();
+}
+template <int NC>
+hipError_t launch_cs16(const float* J, int64_t ld, int n_good, int64_t n, const _Float16* aop, double sh, double sa,
+                       double* out, double* out_hel, hipStream_t st)
+{
+    hipLaunchKernelGGL(me::colour_sum_f16<NC>, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, st, J, ld, n_good, n,
+                       aop, sh, sa, out, out_hel);
+    return hipGetLastError();
+}
+
+hipError_t colour_sum(const me_handle* h, bool fp64, const void* J, int64_t ld, int n_good, int64_t n, double* out,
+                      double* out_hel, hipStream_t st)
+{
+    const double sh = 1.0 / h->P->colour_den, sa = 1.0 / ((double)h->P->colour_den * h->P->avg);
+    if (fp64) {
+        const double* j = static_cast<const double*>(J);
+        switch (h->P->nc) {
+        case 1: return launch_cs64<1>(j, ld, n_good, n, h->d_aop64, sh, sa, out, out_hel, st);
+        case 2: return launch_cs64<2>(j, ld, n_good, n, h->d_aop64, sh, sa, out, out_hel, st);
+        case 6: return launch_cs64<6>(j, ld, n_good, n, h->d_aop64, sh, sa, out, out_hel, st);
+        case 24: return launch_cs64<24>(j, ld, n_good, n, h->d_aop64, sh, sa, out, out_hel, st);
+        case 120: return launch_cs64<120>(j, ld, n_good, n, h->d_aop64, sh, sa, out, out_hel, st);
+        }
+    } else {
+        const float* j = static_cast<const float*>(J);
+        switch (h->P->nc) {
+        case 1: return launch_cs16<1>(j, ld, n_good, n, h->d_aop16, sh, sa, out, out_hel, st);
+        case 2: return launch_cs16<2>(j, ld, n_good, n, h->d_aop16, sh, sa, out, out_hel, st);
+        case 6: return launch_cs16<6>(j, ld, n_good, n, h->d_aop16, sh, sa, out, out_hel, st);
+        case 24: return launch_cs16<24>(j, ld, n_good, n, h->d_aop16, sh, sa, out, out_hel, st);
+        case 120: return launch_cs16<120>(j, ld, n_good, n, h->d_aop16, sh, sa, out, out_hel, st);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int NF>
+hipError_t launch_rambo(uint64_t seed, double sqrt_s, const me::FinalMasses& fm, int64_t evt0, int64_t n, double* out,
+                        hipStream_t st)
+{
+    hipLaunchKernelGGL(me::rambo_kernel<NF>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, seed, sqrt_s, fm,
+                       evt0, n, out);
+    return hipGetLastError();
+}
+
+hipError_t rambo(const me_handle* h, uint64_t seed, double sqrt_s, int64_t evt0, int64_t n, double* out, hipStream_t st)
+{
+    me::FinalMasses fm{};
+    const int nf = h->P->npar - 2;
+    for (int i = 0; i < nf; ++i) fm.m[i] = h->P->final_massive[i] ? h->mt : 0.0;
+    switch (nf) {
+    case 2: return launch_rambo<2>(seed, sqrt_s, fm, evt0, n, out, st);
+    case 3: return launch_rambo<3>(seed, sqrt_s, fm, evt0, n, out, st);
+    case 4: return launch_rambo<4>(seed, sqrt_s, fm, evt0, n, out, st);
+    case 5: return launch_rambo<5>(seed, sqrt_s, fm, evt0, n, out, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+double final_mass_sum(const me_handle* h)
+{
+    double s = 0.0;
+    for (int i = 0; i < h->P->npar - 2; ++i) s += h->P->final_massive[i] ? h->mt : 0.0;
+    return s;
+}
+
+// amplitude kernel + colour sum for events [0, n) of `mom`, in chunks through `jamp`
+int run_chunks(me_handle* h, bool fp64, const signed char* hel, int n_good, int64_t chunk, const double* mom,
+               int64_t n, double* out, double* out_hel, void* jamp, hipStream_t st)
+{
+    const me::ProcessDesc* P = h->P;
+    for (int64_t c0 = 0; c0 < n; c0 += chunk) {
+        const int64_t nc = std::min(chunk, n - c0);
+        const int64_t ld = (nc + 63) / 64 * 64;
+        const double* m = mom + c0 * P->npar * 4;
+        hipError_t e = fp64 ? P->launch_f64(m, nc, ld, hel, n_good, h->mt, h->g, static_cast<double*>(jamp), st)
+                            : P->launch_f32(m, nc, ld, hel, n_good, h->mt, h->g, static_cast<float*>(jamp), st);
+        if (e != hipSuccess) return fail(ME_EHIP, std::string("amplitude kernel: ") + hipGetErrorString(e));
+        e = colour_sum(h, fp64, jamp, ld, n_good, nc, out + c0, out_hel ? out_hel + c0 * n_good : nullptr, st);
+        if (e != hipSuccess) return fail(ME_EHIP, std::string("colour-sum kernel: ") + hipGetErrorString(e));
+    }
+    return ME_OK;
+}
+
+void free_handle(me_handle* h)
+{
+    if (!h) return;
+    for (auto& kv : h->scratch) {
+        if (kv.second.ptr) {
+            (void)hipStreamSynchronize(kv.first);
+            (void)hipFree(kv.second.ptr);
+        }
+    }
+    if (h->d_hel_good) (void)hipFree(h->d_hel_good);
+    if (h->d_aop64) (void)hipFree(h->d_aop64);
+    if (h->d_aop16) (void)hipFree(h->d_aop16);
+    delete h;
+}
+
+// colour matrix as matrix-core A operands (see colorsum.hpp for the layouts)
+int upload_colour(me_handle* h)
+{
+    const me::ProcessDesc* P = h->P;
+    const int NC = P->nc;
+    const int MT = (NC + 15) / 16, KT = (NC + 3) / 4, KB = MT;
+    auto C = [&](int r, int c) -> double { return (r < NC && c < NC) ? P->colour_num[r * NC + c] : 0.0; };
+    std::vector<double> a64((size_t)MT * KT * 64);
+    for (int mt = 0; mt < MT; ++mt)
+        for (int kt = 0; kt < KT; ++kt)
+            for (int l = 0; l < 64; ++l) a64[((size_t)mt * KT + kt) * 64 + l] = C(16 * mt + l % 16, 4 * kt + l / 16);
+    std::vector<_Float16> a16((size_t)MT * KB * 64 * 4);
+    for (int mt = 0; mt < MT; ++mt)
+        for (int kb = 0; kb < KB; ++kb)
+            for (int l = 0; l < 64; ++l)
+                for (int t = 0; t < 4; ++t) {
+                    const double v = C(16 * mt + l % 16, 16 * kb + 4 * (l / 16) + t);
+                    const _Float16 x = (_Float16)v;
+                    if ((double)x != v) return fail(ME_EINVAL, "colour matrix numerator not exact in FP16");
+                    a16[(((size_t)mt * KB + kb) * 64 + l) * 4 + t] = x;
+                }
+    if (hipMalloc(&h->d_aop64, a64.size() * sizeof(double)) != hipSuccess ||
+        hipMalloc(&h->d_aop16, a16.size() * sizeof(_Float16)) != hipSuccess)
+        return fail(ME_ENOMEM, "hipMalloc of the colour tables failed");
+    if (hipMemcpy(h->d_aop64, a64.data(), a64.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->d_aop16, a16.data(), a16.size() * sizeof(_Float16), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(ME_EHIP, "upload of the colour tables failed");
+    h->bytes_resident += a64.size() * sizeof(double) + a16.size() * sizeof(_Float16);
+    return ME_OK;
+}
+
+// helicity-filter pre-pass: every helicity on PREPASS_EVENTS fixed RAMBO events, in FP64
+int helicity_prepass(me_handle* h, hipStream_t st)
+{
+    const me::ProcessDesc* P = h->P;
+    const int nhel = P->nhel, npar = P->npar;
+    std::vector<signed char> all((size_t)nhel * npar);
+    for (int hh = 0; hh < nhel; ++hh)
+        for (int i = 0; i < npar; ++i) all[(size_t)hh * npar + i] = ((hh >> (npar - 1 - i)) & 1) ? 1 : -1;
+    const int64_t n = PREPASS_EVENTS;
+    const double sqrt_s = P->coupling ? 1500.0 : 500.0;
+    signed char* d_all = nullptr;
+    double *d_mom = nullptr, *d_out = nullptr, *d_hel = nullptr, *d_jamp = nullptr;
+    const size_t jbytes = (size_t)nhel * 2 * P->nc * n * sizeof(double);
+    int rc = ME_OK;
+    if (hipMalloc(&d_all, all.size()) != hipSuccess || hipMalloc(&d_mom, n * npar * 4 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&d_out, n * sizeof(double)) != hipSuccess ||
+        hipMalloc(&d_hel, (size_t)n * nhel * sizeof(double)) != hipSuccess || hipMalloc(&d_jamp, jbytes) != hipSuccess) {
+        rc = fail(ME_ENOMEM, "hipMalloc for the helicity pre-pass failed");
+    }
+    std::vector<double> out(n), hel((size_t)n * nhel);
+    if (rc == ME_OK && hipMemcpyAsync(d_all, all.data(), all.size(), hipMemcpyHostToDevice, st) != hipSuccess)
+        rc = fail(ME_EHIP, "upload of the helicity table failed");
+    if (rc == ME_OK && rambo(h, PREPASS_SEED, std::max(sqrt_s, 2.0 * final_mass_sum(h) + 1.0), 0, n, d_mom, st) != hipSuccess)
+        rc = fail(ME_EHIP, "pre-pass RAMBO launch failed");
+    if (rc == ME_OK) rc = run_chunks(h, true, d_all, nhel, n, d_mom, n, d_out, d_hel, d_jamp, st);
+    if (rc == ME_OK) {
+        if (hipMemcpyAsync(out.data(), d_out, n * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(hel.data(), d_hel, hel.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            rc = fail(ME_EHIP, "pre-pass copy-back failed");
+    }
+    if (d_all) (void)hipFree(d_all);
+    if (d_mom) (void)hipFree(d_mom);
+    if (d_out) (void)hipFree(d_out);
+    if (d_hel) (void)hipFree(d_hel);
+    if (d_jamp) (void)hipFree(d_jamp);
+    if (rc != ME_OK) return rc;
+    h->hel_ratio.assign(nhel, 0.0);
+    for (int64_t e = 0; e < n; ++e) {
+        const double tot = out[e] * P->avg;
+        if (!(tot > 0.0)) continue;
+        for (int hh = 0; hh < nhel; ++hh) h->hel_ratio[hh] = std::max(h->hel_ratio[hh], hel[e * nhel + hh] / tot);
+    }
+    h->h_hel_good.clear();
+    for (int hh = 0; hh < nhel; ++hh)
+        if (h->hel_ratio[hh] > PREPASS_THRESHOLD)
+            h->h_hel_good.insert(h->h_hel_good.end(), all.begin() + (size_t)hh * npar, all.begin() + (size_t)(hh + 1) * npar);
+    h->n_good = (int)(h->h_hel_good.size() / npar);
+    if (h->n_good == 0) return fail(ME_EINVAL, "helicity pre-pass found no contributing helicity");
+    if (hipMalloc(&h->d_hel_good, h->h_hel_good.size()) != hipSuccess)
+        return fail(ME_ENOMEM, "hipMalloc of the helicity list failed");
+    if (hipMemcpy(h->d_hel_good, h->h_hel_good.data(), h->h_hel_good.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(ME_EHIP, "upload of the helicity list failed");
+    h->bytes_resident += h->h_hel_good.size();
+    return ME_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* me_last_error(void) { return g_err.c_str(); }
+
+me_handle* me_create(const char* process, const double* masses, int n_masses, const double* couplings,
+                     int n_couplings, int precision, void* stream)
+{
+    g_err.clear();
+    if (!process) { fail(ME_EINVAL, "process is NULL"); return nullptr; }
+    const me::ProcessDesc* P = find_process(process);
+    if (!P) { fail(ME_ENOPROC, std::string("unknown process: ") + process); return nullptr; }
+    if (precision != ME_FP64 && precision != ME_MIXED_FP16) { fail(ME_EINVAL, "unknown precision"); return nullptr; }
+    if ((masses && (n_masses < 1 || n_masses > 2)) || (couplings && n_couplings != 2)) {
+        fail(ME_EINVAL, "masses: {m_t} or {m_t, w_t}; couplings: {alpha_em, alpha_s}");
+        return nullptr;
+    }
+    me_handle* h = new me_handle();
+    h->P = P;
+    h->precision = precision;
+    if (masses) {
+        h->mt = masses[0];
+        if (n_masses == 2 && masses[1] != 0.0) {
+            fail(ME_EINVAL, "non-zero top width is not supported");
+            delete h;
+            return nullptr;
+        }
+    }
+    if (couplings) {
+        h->alpha_em = couplings[0];
+        h->alpha_s = couplings[1];
+    }
+    if (!(h->mt > 0.0) || !(h->alpha_em > 0.0) || !(h->alpha_s > 0.0)) {
+        fail(ME_EINVAL, "masses and couplings must be positive");
+        delete h;
+        return nullptr;
+    }
+    h->g = std::sqrt(4.0 * PI * (P->coupling ? h->alpha_s : h->alpha_em));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (upload_colour(h) != ME_OK || helicity_prepass(h, st) != ME_OK) {
+        std::string msg = g_err;
+        free_handle(h);
+        g_err = msg;
+        return nullptr;
+    }
+    const size_t rsize = (precision == ME_FP64) ? sizeof(double) : sizeof(float);
+    h->bytes_per_event = (size_t)h->n_good * 2 * P->nc * rsize;
+    int64_t chunk = (int64_t)(SCRATCH_CAP / h->bytes_per_event) / 64 * 64;
+    h->chunk = std::max<int64_t>(64, chunk);
+    return h;
+}
+
+void me_destroy(me_handle* h) { free_handle(h); }
+
+int me_info(const me_handle* h, me_info_t* out)
+{
+    if (!h || !out) return fail(ME_EINVAL, "NULL argument");
+    const me::ProcessDesc* P = h->P;
+    out->n_par = P->npar;
+    out->n_diagrams = P->n_diagrams;
+    out->n_amplitudes = P->n_amplitudes;
+    out->n_colors = P->nc;
+    out->n_hel = P->nhel;
+    out->n_good_hel = h->n_good;
+    out->precision = h->precision;
+    out->avg_factor = P->avg;
+    out->sym_factor = P->sym;
+    out->flops_amp_lane = P->flops_lane;
+    out->flops_colour_lane = 4.0 * P->nc * P->nc + 4.0 * P->nc + 1.0;
+    out->bytes_resident = (int64_t)h->bytes_resident;
+    out->bytes_per_event_scratch = (int64_t)h->bytes_per_event;
+    out->chunk_events = h->chunk;
+    return ME_OK;
+}
+
+int me_good_helicities(const me_handle* h, signed char* out)
+{
+    if (!h || !out) return fail(ME_EINVAL, "NULL argument");
+    std::memcpy(out, h->h_hel_good.data(), h->h_hel_good.size());
+    return h->n_good;
+}
+
+int me_helicity_ratios(const me_handle* h, double* out)
+{
+    if (!h || !out) return fail(ME_EINVAL, "NULL argument");
+    std::memcpy(out, h->hel_ratio.data(), h->hel_ratio.size() * sizeof(double));
+    return (int)h->hel_ratio.size();
+}
+
+int rambo_momenta(const me_handle* h, uint64_t seed, double sqrt_s, int64_t evt0, int64_t n_evt, double* out,
+                  void* stream)
+{
+    if (!h) return fail(ME_EINVAL, "handle is NULL");
+    if (n_evt < 0 || evt0 < 0) return fail(ME_EINVAL, "negative event count or offset");
+    if (n_evt == 0) return ME_OK;
+    if (!(sqrt_s > final_mass_sum(h))) return fail(ME_EINVAL, "sqrt_s must exceed the sum of final-state masses");
+    if (!is_device_pointer(out)) return fail(ME_EINVAL, "out must be a device pointer");
+    hipError_t e = rambo(h, seed, sqrt_s, evt0, n_evt, out, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail(ME_EHIP, std::string("RAMBO kernel: ") + hipGetErrorString(e));
+    return ME_OK;
+}
+
+int me_sigma_hel(me_handle* h, const double* momenta, int64_t n_evt, double* out_me2, double* out_hel, void* stream)
+{
+    if (!h) return fail(ME_EINVAL, "handle is NULL");
+    if (n_evt < 0) return fail(ME_EINVAL, "negative event count");
+    if (n_evt == 0) return ME_OK;
+    if (!is_device_pointer(momenta) || !is_device_pointer(out_me2) || (out_hel && !is_device_pointer(out_hel)))
+        return fail(ME_EINVAL, "momenta and outputs must be device pointers");
+    if (reinterpret_cast<uintptr_t>(momenta) % 16 != 0) return fail(ME_EINVAL, "momenta must be 16-byte aligned");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t chunk = std::min<int64_t>(h->chunk, (n_evt + 63) / 64 * 64);
+    const size_t need = (size_t)chunk * h->bytes_per_event;
+    void* jamp = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(h->mu);
+        Scratch& s = h->scratch[st];
+        if (s.bytes < need) {
+            if (s.ptr) {
+                (void)hipStreamSynchronize(st);
+                (void)hipFree(s.ptr);
+                s.ptr = nullptr;
+                s.bytes = 0;
+            }
+            size_t want = std::max(need, std::min<size_t>(SCRATCH_CAP, 2 * s.bytes));
+            if (hipMalloc(&s.ptr, want) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(ME_ENOMEM, "hipMalloc of the jamp scratch failed");
+            }
+            s.bytes = want;
+        }
+        jamp = s.ptr;
+    }
+    return run_chunks(h, h->precision == ME_FP64, h->d_hel_good, h->n_good, chunk, momenta, n_evt, out_me2, out_hel,
+                      jamp, st);
+}
+
+int me_sigma(me_handle* h, const double* momenta, int64_t n_evt, double* out_me2, void* stream)
+{
+    return me_sigma_hel(h, momenta, n_evt, out_me2, nullptr, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,39 @@
+// process.hpp -- descriptor of a generated process, shared by the generated kernels and the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace me {
+
+typedef hipError_t (*amp_launch_f64)(const double* mom, int64_t n_evt, int64_t ld, const signed char* hel,
+                                     int n_good, double mt, double g, double* jamp, hipStream_t st);
+typedef hipError_t (*amp_launch_f32)(const double* mom, int64_t n_evt, int64_t ld, const signed char* hel,
+                                     int n_good, double mt, double g, float* jamp, hipStream_t st);
+
+struct ProcessDesc {
+    const char* name;
+    int npar;          // particles, incoming first
+    int nc;            // colour flows (jamps)
+    int nhel;          // helicity combinations, 2^npar
+    int avg;           // initial-state spin x colour average
+    int sym;           // identical final-state particle factor (reported, not applied)
+    int coupling;      // 0: alpha_em (QED), 1: alpha_s (QCD)
+    const int* colour_num;     // nc x nc integer numerators of the colour matrix
+    int colour_den;            // their common denominator
+    const int* final_massive;  // npar-2 flags: final-state particle carries the top mass
+    const int* orderings;      // nc x (gluons): the gluon order of each colour flow
+    int n_diagrams;            // Feynman diagrams
+    int n_amplitudes;          // vertex contractions (four-gluon vertices count 3)
+    double flops_lane;         // algorithmic flops of the amplitude kernel per (event, helicity)
+    amp_launch_f64 launch_f64;
+    amp_launch_f32 launch_f32;
+};
+
+const ProcessDesc* process_ee_mumu();
+const ProcessDesc* process_gg_tt();
+const ProcessDesc* process_gg_ttg();
+const ProcessDesc* process_gg_ttgg();
+const ProcessDesc* process_gg_ttggg();
+const ProcessDesc* process_gg_gg();
+
+}  // namespace me

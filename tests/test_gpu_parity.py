@@ -1,0 +1,145 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle on the same seeded
+inputs (momenta from the oracle's RAMBO, uploaded).
+
+FP64 bar: per-event relative error <= 1e-12.  Events where FP64 itself is ill-conditioned
+(the long-double oracle differs from the double oracle by more than 1e-13) are judged
+against the long-double value with the bound 1e-12 + 4 x (that difference); they are
+counted and reported, never dropped.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from tests import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def make_process(name, precision="fp64"):
+    from paper_2210_11122_amd import Process
+    return Process(name, m_top=W.M_TOP, alpha_em=W.ALPHA_EM, alpha_s=W.ALPHA_S, precision=precision)
+
+
+def check_fp64(name, p, got):
+    want = oracle.me_batch(name, p, params=W.PARAMS)
+    rel = np.abs(got / want - 1)
+    bad = np.where(rel > TOL)[0]
+    n_ill = 0
+    for i in bad:
+        ld = oracle.me(name, p[i], params=W.PARAMS, precision="long double")
+        kappa = abs(want[i] / ld - 1)
+        n_ill += 1
+        assert abs(got[i] / ld - 1) <= TOL + 4 * kappa, (name, int(i), float(got[i]), float(want[i]), float(ld))
+    print(f"{name}: {len(p)} events, max rel {rel.max():.2e}, median {np.median(rel):.2e}, "
+          f"ill-conditioned {n_ill}", flush=True)
+    return rel
+
+
+CASES = [("ee_mumu", 8192), ("gg_tt", 4093), ("gg_ttg", 1031), ("gg_ttgg", 157), ("gg_gg", 1000)]
+
+
+@pytest.mark.parametrize("name,n", CASES)
+def test_fp64_matches_oracle(name, n):
+    print(f"case fp64 {name} n={n}", flush=True)
+    p = oracle.rambo(W.SEED, W.sqrt_s(name), W.final_masses(name), n)
+    proc = make_process(name)
+    got = proc.sigma(torch.from_numpy(p).cuda()).cpu().numpy()
+    check_fp64(name, p, got)
+
+
+@pytest.mark.parametrize("name", ["gg_tt", "gg_ttg", "gg_ttgg"])
+def test_per_helicity_matches_oracle(name):
+    print(f"case per-helicity {name}", flush=True)
+    n = 5
+    p = oracle.rambo(3, W.sqrt_s(name), W.final_masses(name), n)
+    proc = make_process(name)
+    tot, hel = proc.sigma(torch.from_numpy(p).cuda(), per_helicity=True)
+    hel = hel.cpu().numpy()
+    good = proc.good_helicities()
+    npar = W.n_par(name)
+    for e in range(n):
+        _, ref = oracle.me(name, p[e], params=W.PARAMS, per_helicity=True)
+        scale = ref.max()
+        for k, lam in enumerate(good):
+            hh = sum(((l + 1) // 2) << (npar - 1 - i) for i, l in enumerate(lam))
+            assert abs(hel[e, k] - ref[hh]) <= 1e-12 * scale
+
+
+def test_ee_mumu_helicity_filter_keeps_four():
+    proc = make_process("ee_mumu")
+    good = proc.good_helicities()
+    assert sorted(good) == sorted([(-1, 1, -1, 1), (-1, 1, 1, -1), (1, -1, -1, 1), (1, -1, 1, -1)])
+
+
+@pytest.mark.parametrize("name", ["gg_tt", "gg_ttg", "gg_ttgg"])
+def test_filtered_equals_unfiltered_oracle_on_held_out_events(name):
+    """the oracle sums all helicities; the GPU only the pre-pass survivors"""
+    p = oracle.rambo(12345, W.sqrt_s(name), W.final_masses(name), 64)
+    proc = make_process(name)
+    got = proc.sigma(torch.from_numpy(p).cuda()).cpu().numpy()
+    want = oracle.me_batch(name, p, params=W.PARAMS)
+    assert np.max(np.abs(got / want - 1)) <= TOL
+
+
+@pytest.mark.parametrize("name", W.ALL)
+def test_rambo_gpu_matches_cpu(name):
+    proc = make_process(name) if name != "gg_ttggg" else None
+    if proc is None:
+        pytest.skip("gg_ttggg handled in its own test module")
+    n = 4099
+    for seed in (0, 77):
+        g = proc.rambo(seed, W.sqrt_s(name), n).cpu().numpy()
+        c = oracle.rambo(seed, W.sqrt_s(name), W.final_masses(name), n)
+        assert np.max(np.abs(g - c)) <= 1e-13 * W.sqrt_s(name)
+    g = proc.rambo(5, W.sqrt_s(name), 100, evt0=1000).cpu().numpy()
+    c = oracle.rambo(5, W.sqrt_s(name), W.final_masses(name), 100, evt0=1000)
+    assert np.max(np.abs(g - c)) <= 1e-13 * W.sqrt_s(name)
+
+
+@pytest.mark.parametrize("name", ["gg_tt", "gg_ttg", "gg_ttgg"])
+def test_mixed_precision_error_statistics(name):
+    n = {"gg_tt": 4096, "gg_ttg": 2048, "gg_ttgg": 512}[name]
+    p = oracle.rambo(W.SEED, W.sqrt_s(name), W.final_masses(name), n)
+    x = torch.from_numpy(p).cuda()
+    ref = make_process(name).sigma(x).cpu().numpy()
+    mix = make_process(name, "mixed_fp16").sigma(x).cpu().numpy()
+    rel = np.abs(mix / ref - 1)
+    print(f"{name} mixed_fp16: max {rel.max():.2e} median {np.median(rel):.2e} "
+          f"p99 {np.quantile(rel, 0.99):.2e}", flush=True)
+    assert np.median(rel) < 1e-5 and np.quantile(rel, 0.99) < 1e-3
+
+
+def test_empty_and_single_event():
+    proc = make_process("gg_ttg")
+    x = torch.empty((0, 5, 4), dtype=torch.float64, device="cuda")
+    assert proc.sigma(x).numel() == 0
+    p = oracle.rambo(9, 1500.0, W.final_masses("gg_ttg"), 1)
+    got = proc.sigma(torch.from_numpy(p).cuda()).cpu().numpy()
+    assert abs(got[0] / oracle.me("gg_ttg", p[0], params=W.PARAMS) - 1) <= TOL
+
+
+def test_abi_rejects_bad_arguments():
+    import ctypes
+    from paper_2210_11122_amd import binding
+    L = binding.load()
+    assert not L.me_create(b"no_such_process", None, 0, None, 0, 0, None)
+    assert "unknown process" in binding.last_error()
+    proc = make_process("gg_tt")
+    host = np.zeros((4, 4, 4))
+    out = torch.empty(4, dtype=torch.float64, device="cuda")
+    rc = L.me_sigma(proc._h, ctypes.c_void_p(host.ctypes.data), 4, ctypes.c_void_p(out.data_ptr()), None)
+    assert rc == -1 and "device pointer" in binding.last_error()
+    x = torch.zeros((4, 4, 4), dtype=torch.float64, device="cuda")
+    assert L.me_sigma(proc._h, ctypes.c_void_p(x.data_ptr()), -1, ctypes.c_void_p(out.data_ptr()), None) == -1
+    assert L.me_sigma(None, ctypes.c_void_p(x.data_ptr()), 4, ctypes.c_void_p(out.data_ptr()), None) == -1
+    assert L.rambo_momenta(proc._h, 0, 300.0, 0, 4, ctypes.c_void_p(x.data_ptr()), None) == -1
+
+
+def test_info_counts():
+    for name, nd, nc, nh in [("ee_mumu", 1, 1, 16), ("gg_tt", 3, 2, 16), ("gg_ttg", 16, 6, 32),
+                             ("gg_ttgg", 123, 24, 64)]:
+        i = make_process(name).info
+        assert (i["n_diagrams"], i["n_colors"], i["n_hel"]) == (nd, nc, nh)

@@ -92,6 +92,14 @@ int me_good_helicities(const me_handle *h, signed char *out);
  * n_hel helicity combinations (index: particle i's bit (l+1)/2 at 2^(n_par-1-i)). */
 int me_helicity_ratios(const me_handle *h, double *out);
 
+/* Launch timing, for measurement: with enable != 0, every later me_sigma call records a
+ * HIP event pair around each kernel launch on its stream.  Each call returns (and clears)
+ * what was recorded since the previous call: total milliseconds and launch counts of the
+ * amplitude kernel and of the colour-sum kernel (it waits for those events).  Any pointer
+ * may be NULL.  Not for use while another thread calls me_sigma on the same handle. */
+int me_profile(me_handle *h, int enable, double *ms_amp, double *ms_colour, int64_t *n_amp,
+               int64_t *n_colour);
+
 const char *me_last_error(void); /* thread-local; valid until the thread's next call */
 
 void me_destroy(me_handle *h); /* frees the handle and its device memory; NULL-safe */

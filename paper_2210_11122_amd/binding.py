@@ -33,7 +33,7 @@ class MeInfo(ctypes.Structure):
 
 
 EXPORTS = ["me_create", "me_destroy", "me_info", "me_last_error", "rambo_momenta", "me_sigma",
-           "me_sigma_hel", "me_good_helicities", "me_helicity_ratios"]
+           "me_sigma_hel", "me_good_helicities", "me_helicity_ratios", "me_profile"]
 
 _lib = None
 
@@ -57,6 +57,7 @@ def load():
     L.me_sigma_hel.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp]
     L.me_good_helicities.argtypes = [vp, ctypes.POINTER(ctypes.c_byte)]
     L.me_helicity_ratios.argtypes = [vp, D]
+    L.me_profile.argtypes = [vp, ctypes.c_int, D, D, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
     _lib = L
     return L
 
@@ -133,6 +134,15 @@ class Process:
         _check(load().me_sigma(self._h, ctypes.c_void_p(momenta.data_ptr()), n, ctypes.c_void_p(out.data_ptr()),
                                _stream_ptr(stream)), "me_sigma")
         return out
+
+    def profile(self, enable):
+        """switch launch timing on/off; returns what was recorded since the last call:
+        (ms amplitude kernel, ms colour sum, launches of each)"""
+        a, c = ctypes.c_double(), ctypes.c_double()
+        na, nc = ctypes.c_int64(), ctypes.c_int64()
+        _check(load().me_profile(self._h, int(enable), ctypes.byref(a), ctypes.byref(c), ctypes.byref(na),
+                                 ctypes.byref(nc)), "me_profile")
+        return a.value, c.value, na.value, nc.value
 
     def good_helicities(self):
         n = self.info["n_good_hel"]

@@ -15,7 +15,7 @@
 // FP32 from the scaled FP32 jamps, unscaled exactly, and summed over helicities in FP64.
 //
 // MFMA operand layouts (lane l, i = l % 16, g = l / 16):
-//   f64 16x16x4:  A[i][g], B[g][i], D[4g + r][i] (r = 0..3)
+//   f64 16x16x4:  A[i][g], B[g][i], D[g + 4r][i] (r = 0..3)
 //   f16 16x16x16: A[i][4g + t], B[4g + t][i] (t = 0..3), D[4g + r][i]
 #pragma once
 #include <hip/hip_runtime.h>
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void colour_sum_f64(const double* __restrict__
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int c = 16 * mt + 4 * g + r;
+                    const int c = 16 * mt + g + 4 * r;
                     if (c < NC) part += Jh[(int64_t)(2 * c + ri) * ld + ec] * d[mt][r];
                 }
         }

@@ -79,6 +79,13 @@ struct me_handle {
     size_t bytes_per_event = 0;
     std::mutex mu;
     std::unordered_map<hipStream_t, Scratch> scratch;
+    // optional launch timing: HIP events recorded around every kernel launch on its stream
+    bool profiling = false;
+    struct Mark {
+        hipEvent_t a, b;
+        int kind;  // 0 amplitude kernel, 1 colour-sum kernel
+    };
+    std::vector<Mark> marks;
 };
 
 namespace {
@@ -159,19 +166,43 @@ double final_mass_sum(const me_handle* h)
     return s;
 }
 
+// start/stop a timed launch when profiling is on (events on the launch stream)
+struct TimedLaunch {
+    me_handle* h;
+    hipStream_t st;
+    int kind;
+    hipEvent_t a = nullptr, b = nullptr;
+    TimedLaunch(me_handle* hh, hipStream_t s, int k, bool on) : h(hh), st(s), kind(k)
+    {
+        if (on && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) (void)hipEventRecord(a, st);
+    }
+    void done()
+    {
+        if (!b) return;
+        (void)hipEventRecord(b, st);
+        std::lock_guard<std::mutex> lk(h->mu);
+        h->marks.push_back({a, b, kind});
+        a = b = nullptr;
+    }
+};
+
 // amplitude kernel + colour sum for events [0, n) of `mom`, in chunks through `jamp`
 int run_chunks(me_handle* h, bool fp64, const signed char* hel, int n_good, int64_t chunk, const double* mom,
-               int64_t n, double* out, double* out_hel, void* jamp, hipStream_t st)
+               int64_t n, double* out, double* out_hel, void* jamp, hipStream_t st, bool timed = false)
 {
     const me::ProcessDesc* P = h->P;
     for (int64_t c0 = 0; c0 < n; c0 += chunk) {
         const int64_t nc = std::min(chunk, n - c0);
         const int64_t ld = (nc + 63) / 64 * 64;
         const double* m = mom + c0 * P->npar * 4;
+        TimedLaunch ta(h, st, 0, timed);
         hipError_t e = fp64 ? P->launch_f64(m, nc, ld, hel, n_good, h->mt, h->g, static_cast<double*>(jamp), st)
                             : P->launch_f32(m, nc, ld, hel, n_good, h->mt, h->g, static_cast<float*>(jamp), st);
+        ta.done();
         if (e != hipSuccess) return fail(ME_EHIP, std::string("amplitude kernel: ") + hipGetErrorString(e));
+        TimedLaunch tc(h, st, 1, timed);
         e = colour_sum(h, fp64, jamp, ld, n_good, nc, out + c0, out_hel ? out_hel + c0 * n_good : nullptr, st);
+        tc.done();
         if (e != hipSuccess) return fail(ME_EHIP, std::string("colour-sum kernel: ") + hipGetErrorString(e));
     }
     return ME_OK;
@@ -185,6 +216,10 @@ void free_handle(me_handle* h)
             (void)hipStreamSynchronize(kv.first);
             (void)hipFree(kv.second.ptr);
         }
+    }
+    for (auto& m : h->marks) {
+        (void)hipEventDestroy(m.a);
+        (void)hipEventDestroy(m.b);
     }
     if (h->d_hel_good) (void)hipFree(h->d_hel_good);
     if (h->d_aop64) (void)hipFree(h->d_aop64);
@@ -415,7 +450,35 @@ int me_sigma_hel(me_handle* h, const double* momenta, int64_t n_evt, double* out
         jamp = s.ptr;
     }
     return run_chunks(h, h->precision == ME_FP64, h->d_hel_good, h->n_good, chunk, momenta, n_evt, out_me2, out_hel,
-                      jamp, st);
+                      jamp, st, h->profiling);
+}
+
+int me_profile(me_handle* h, int enable, double* ms_amp, double* ms_colour, int64_t* n_amp, int64_t* n_colour)
+{
+    if (!h) return fail(ME_EINVAL, "handle is NULL");
+    std::vector<me_handle::Mark> marks;
+    {
+        std::lock_guard<std::mutex> lk(h->mu);
+        marks.swap(h->marks);
+        h->profiling = enable != 0;
+    }
+    double t[2] = {0.0, 0.0};
+    int64_t c[2] = {0, 0};
+    int rc = ME_OK;
+    for (auto& m : marks) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(m.b) != hipSuccess || hipEventElapsedTime(&ms, m.a, m.b) != hipSuccess)
+            rc = fail(ME_EHIP, "reading launch timers failed");
+        t[m.kind] += ms;
+        c[m.kind] += 1;
+        (void)hipEventDestroy(m.a);
+        (void)hipEventDestroy(m.b);
+    }
+    if (ms_amp) *ms_amp = t[0];
+    if (ms_colour) *ms_colour = t[1];
+    if (n_amp) *n_amp = c[0];
+    if (n_colour) *n_colour = c[1];
+    return rc;
 }
 
 int me_sigma(me_handle* h, const double* momenta, int64_t n_evt, double* out_me2, void* stream)

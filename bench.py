@@ -66,10 +66,16 @@ def cpu_baseline(name, n_evt_total, params, budget_s, threads):
     import numpy as np
     import oracle
     from tests import workloads as W
-    probe = oracle.rambo(0, W.sqrt_s(name), W.final_masses(name), 2 * threads)
-    t = time.perf_counter()
-    oracle.me_batch(name, probe, params=params, threads=threads)
-    rate = 2 * threads / max(time.perf_counter() - t, 1e-6)
+    n_probe = 8 * threads
+    while True:
+        probe = oracle.rambo(0, W.sqrt_s(name), W.final_masses(name), n_probe)
+        t = time.perf_counter()
+        oracle.me_batch(name, probe, params=params, threads=threads)
+        dt = time.perf_counter() - t
+        if dt > 0.5 or n_probe >= n_evt_total:
+            break
+        n_probe *= 4
+    rate = n_probe / max(dt, 1e-6)
     n = int(min(n_evt_total, max(threads, rate * budget_s)))
     p = oracle.rambo(0, W.sqrt_s(name), W.final_masses(name), n)
     t = time.perf_counter()
@@ -185,12 +191,22 @@ def main():
     if not args.no_cpu:
         threads = min(16, len(os.sched_getaffinity(0)))
         p, me_cpu, rate, dt = cpu_baseline(name, n_evt, W.PARAMS, args.cpu_seconds, threads)
+        import oracle
         got = p64.sigma(torch.from_numpy(p).cuda()).cpu().numpy()
         rel = np.abs(got / me_cpu - 1)
+        # events beyond the FP64 tolerance go to the long-double referee
+        over = np.where(rel > 1e-12)[0]
+        referee_ok = 0
+        for i in over:
+            ld = oracle.me(name, p[i], params=W.PARAMS, precision="long double")
+            kappa = abs(me_cpu[i] / ld - 1)
+            referee_ok += abs(got[i] / ld - 1) <= 1e-12 + 4 * kappa
         result["cpu_baseline"] = {"value": rate, "unit": "MEs/s", "cores": threads, "kind": "oracle",
                                   "sample": f"first {len(p)} events of the same RAMBO stream, {dt:.1f} s"}
         result["parity_sample"] = {"n": int(len(p)), "max_rel_err": float(rel.max()),
-                                   "median_rel_err": float(np.median(rel)), "tolerance": 1e-12}
+                                   "median_rel_err": float(np.median(rel)), "tolerance": 1e-12,
+                                   "n_over_tolerance": int(len(over)),
+                                   "n_over_tolerance_agreeing_with_long_double_referee": int(referee_ok)}
         log(f"cpu oracle: {rate:.4g} MEs/s on {threads} threads ({len(p)} events); GPU vs oracle max rel {rel.max():.2e}")
 
     print(json.dumps(result), flush=True)

@@ -57,6 +57,24 @@ __device__ __forceinline__ P4 operator-(const P4& a, const P4& b)
 __device__ __forceinline__ P4 operator-(const P4& a) { return {-a.t, -a.x, -a.y, -a.z}; }
 __device__ __forceinline__ double msq(const P4& a) { return a.t * a.t - a.x * a.x - a.y * a.y - a.z * a.z; }
 
+// 1/x and 1/sqrt(x) in double: the hardware estimate refined by two Newton steps (within
+// an ulp or two of the correctly rounded result, without the IEEE division sequence)
+__device__ __forceinline__ double rcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double h = 0.5 * x;
+    y = y * __builtin_fma(-h * y, y, 1.5);
+    return y * __builtin_fma(-h * y, y, 1.5);
+}
+
 template <class R>
 struct W4 {
     cx<R> c[4];
@@ -88,14 +106,15 @@ __device__ __forceinline__ cx<R> dot(const W4<R>& a, const R4<R>& k)
 // two-component helicity eigenstates of sigma.p/|p|; (0,1) / (-1,0) for p along -z
 __device__ __forceinline__ void chi2(const P4& p, int lam, double out[4])
 {
-    double pp = sqrt(p.x * p.x + p.y * p.y + p.z * p.z);
-    double d = (p.z >= 0.0) ? pp + p.z : (p.x * p.x + p.y * p.y) / (pp - p.z);
+    double pp2 = p.x * p.x + p.y * p.y + p.z * p.z;
+    double pp = pp2 * rsqrt_nr(pp2);
+    double d = (p.z >= 0.0) ? pp + p.z : (p.x * p.x + p.y * p.y) * rcp(pp - p.z);
     if (!(d > 0.0)) {
         if (lam > 0) { out[0] = 0; out[1] = 0; out[2] = 1; out[3] = 0; }
         else { out[0] = -1; out[1] = 0; out[2] = 0; out[3] = 0; }
         return;
     }
-    double nrm = 1.0 / sqrt(2.0 * pp * d);
+    double nrm = rsqrt_nr(2.0 * pp * d);
     if (lam > 0) { out[0] = d * nrm; out[1] = 0; out[2] = p.x * nrm; out[3] = p.y * nrm; }
     else { out[0] = -p.x * nrm; out[1] = p.y * nrm; out[2] = d * nrm; out[3] = 0; }
 }
@@ -106,8 +125,8 @@ __device__ __forceinline__ W4<R> ext_ubar(const P4& p, double m, int lam)
 {
     double c[4];
     chi2(p, lam, c);
-    double wp = sqrt(p.t + sqrt(p.x * p.x + p.y * p.y + p.z * p.z));
-    double wm = (m == 0.0) ? 0.0 : m / wp;
+    double ep = p.t + sqrt(p.x * p.x + p.y * p.y + p.z * p.z), iw = rsqrt_nr(ep);
+    double wp = ep * iw, wm = m * iw;
     double up = lam > 0 ? wm : wp, lo = lam > 0 ? wp : wm;
     W4<R> w;
     w.c[0] = {(R)(lo * c[0]), (R)(-lo * c[1])};
@@ -122,8 +141,8 @@ __device__ __forceinline__ W4<R> ext_u(const P4& p, double m, int lam)
 {
     double c[4];
     chi2(p, lam, c);
-    double wp = sqrt(p.t + sqrt(p.x * p.x + p.y * p.y + p.z * p.z));
-    double wm = (m == 0.0) ? 0.0 : m / wp;
+    double ep = p.t + sqrt(p.x * p.x + p.y * p.y + p.z * p.z), iw = rsqrt_nr(ep);
+    double wp = ep * iw, wm = m * iw;
     double up = lam > 0 ? wm : wp, lo = lam > 0 ? wp : wm;
     W4<R> w;
     w.c[0] = {(R)(up * c[0]), (R)(up * c[1])};
@@ -138,8 +157,8 @@ __device__ __forceinline__ W4<R> ext_v(const P4& p, double m, int lam)
 {
     double c[4];
     chi2(p, -lam, c);
-    double wp = sqrt(p.t + sqrt(p.x * p.x + p.y * p.y + p.z * p.z));
-    double wm = (m == 0.0) ? 0.0 : m / wp;
+    double ep = p.t + sqrt(p.x * p.x + p.y * p.y + p.z * p.z), iw = rsqrt_nr(ep);
+    double wp = ep * iw, wm = m * iw;
     double wl = lam > 0 ? wp : wm, wml = lam > 0 ? wm : wp;
     double up = -lam * wl, lo = lam * wml;
     W4<R> w;
@@ -165,10 +184,15 @@ __device__ __forceinline__ W4<R> ext_vbar(const P4& p, double m, int lam)
 template <class R>
 __device__ __forceinline__ W4<R> ext_vec(const P4& k, int lam, bool outgoing)
 {
-    double kt = sqrt(k.x * k.x + k.y * k.y);
-    double kk = sqrt(kt * kt + k.z * k.z);
-    double ct = k.z / kk, st = kt / kk, cp = 1.0, sp = 0.0;
-    if (kt > 0.0) { cp = k.x / kt; sp = k.y / kt; }
+    double kt2 = k.x * k.x + k.y * k.y;
+    double ikk = rsqrt_nr(kt2 + k.z * k.z);
+    double ct = k.z * ikk, st = 0.0, cp = 1.0, sp = 0.0;
+    if (kt2 > 0.0) {
+        double ikt = rsqrt_nr(kt2);
+        st = kt2 * ikt * ikk;
+        cp = k.x * ikt;
+        sp = k.y * ikt;
+    }
     const double r = 0.70710678118654752440;
     const double s = outgoing ? -r : r;
     W4<R> w;
@@ -251,21 +275,21 @@ __device__ __forceinline__ W4<R> qslash_row(const R4<R>& q, R m, R f, const W4<R
 template <class R>
 __device__ __forceinline__ W4<R> fstr_v(const W4<R>& psi, const W4<R>& G, const P4& q, double m, double g)
 {
-    double f = -g / (msq(q) - m * m);
+    double f = -g * rcp(msq(q) - m * m);
     return qslash_col<R>(rnd<R>(q), (R)m, (R)f, gslash_col<R>(G, psi));
 }
 // quark-side string extended by one vertex: ubar (i g gamma.G) S(q)
 template <class R>
 __device__ __forceinline__ W4<R> fstr_u(const W4<R>& ub, const W4<R>& G, const P4& q, double m, double g)
 {
-    double f = -g / (msq(q) - m * m);
+    double f = -g * rcp(msq(q) - m * m);
     return qslash_row<R>(rnd<R>(q), (R)m, (R)f, gslash_row<R>(ub, G));
 }
 // gluon emitted by the pair (ubar, psi): (-i/P^2)(i g ubar gamma^mu psi) = (g/P^2) ubar gamma^mu psi
 template <class R>
 __device__ __forceinline__ W4<R> jf(const W4<R>& u, const W4<R>& s, const P4& P, double g)
 {
-    R f = (R)(g / msq(P));
+    R f = (R)(g * rcp(msq(P)));
     cx<R> u0s2 = u.c[0] * s.c[2], u1s3 = u.c[1] * s.c[3], u2s0 = u.c[2] * s.c[0], u3s1 = u.c[3] * s.c[1];
     cx<R> u0s3 = u.c[0] * s.c[3], u1s2 = u.c[1] * s.c[2], u2s1 = u.c[2] * s.c[1], u3s0 = u.c[3] * s.c[0];
     W4<R> o;
@@ -280,7 +304,7 @@ __device__ __forceinline__ W4<R> jf(const W4<R>& u, const W4<R>& s, const P4& P,
 template <class R>
 __device__ __forceinline__ W4<R> vvv_cur(const W4<R>& J1, const P4& k1, const W4<R>& J2, const P4& k2, double g)
 {
-    double f = g / msq(k1 + k2);
+    double f = g * rcp(msq(k1 + k2));
     R4<R> a = rnd<R>(k1 - k2), b = rnd<R>(k1 + k2 + k2), c = rnd<R>(k1 + k1 + k2);
     cx<R> d12 = dot(J1, J2), d1b = dot(J1, b), d2c = dot(J2, c);
     R ar[4] = {a.t, a.x, a.y, a.z};
@@ -297,7 +321,7 @@ __device__ __forceinline__ W4<R> vvv_cur(const W4<R>& J1, const P4& k1, const W4
 template <class R, int S>
 __device__ __forceinline__ W4<R> vvvv_cur(const W4<R>& Ja, const W4<R>& Jb, const W4<R>& Jc, const P4& P, double g)
 {
-    R f = (R)(-g * g / msq(P));
+    R f = (R)(-g * g * rcp(msq(P)));
     W4<R> o;
     if (S == 0) {
         cx<R> ac = dot(Ja, Jc), ab = dot(Ja, Jb);
@@ -388,7 +412,8 @@ namespace me {
 // use (volatile: the compiler neither caches nor hoists it, so no four-momentum stays live)
 __device__ __forceinline__ P4 lds_p4(const double* lds, int i, int lane)
 {
-    const volatile double* v = lds;
+    typedef __attribute__((address_space(3))) const volatile double lds_double;
+    lds_double* v = (lds_double*)lds;
     return {v[(4 * i) * 64 + lane], v[(4 * i + 1) * 64 + lane], v[(4 * i + 2) * 64 + lane],
             v[(4 * i + 3) * 64 + lane]};
 }
@@ -397,5 +422,13 @@ template <class R>
 __device__ __forceinline__ void lds_add(R* p, R v)
 {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+// jamp update in LDS: atomic add for double (ds_add_f64); plain read-add-write for float
+// (the FP32 LDS atomic add is much slower than the FP64 one on gfx950)
+template <class R>
+__device__ __forceinline__ void jamp_add(R* p, R v)
+{
+    if constexpr (sizeof(R) == 8) lds_add<R>(p, v);
+    else *p += v;
 }
 }  // namespace me

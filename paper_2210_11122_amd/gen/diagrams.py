@@ -277,7 +277,9 @@ class Plan:
 def node_size(key, remat_ext=False):
     """registers (FP64 VGPRs) a computed node occupies while live; external wavefunctions
     that are recomputed at each use occupy none"""
-    if key[0].startswith("EXT") and remat_ext:
+    if key[0].startswith("EXT") and (remat_ext is True or
+                                     (remat_ext == "gluons" and key[0] in ("EXT_G", "EXT_ROOT")) or
+                                     (remat_ext == "spinors" and key[0] in ("EXT_U", "EXT_V"))):
         return 0
     if key[0] == "EXT_G" or key[0] == "EXT_ROOT":
         return 14   # eps^0 = 0 and Im eps^3 = 0

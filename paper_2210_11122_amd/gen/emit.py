@@ -129,9 +129,18 @@ class Process:
 
         counted = set()
 
+        def remat(kind):
+            if remat_ext is True:
+                return True
+            if remat_ext == "gluons":
+                return kind in ("EXT_G", "EXT_ROOT")
+            if remat_ext == "spinors":
+                return kind in ("EXT_U", "EXT_V")
+            return False
+
         def emit(key):
             kind = key[0]
-            if kind.startswith("EXT") and remat_ext:
+            if kind.startswith("EXT") and remat(kind):
                 code, fl = ext_code(key)
                 if key not in counted:
                     counted.add(key)
@@ -237,12 +246,18 @@ class Process:
         return 4 * FLOPS["ext_spinor"] + FLOPS["p4add"] + FLOPS["jf"] + FLOPS["amp_ffv"] + FLOPS["jamp"]
 
     # -----------------------------------------------------------------------------------
-    def source(self, jamps_in_lds=None, remat_ext=None):
+    def source(self, jamps_in_lds=None, remat_ext=None, jamp_mode="auto"):
+        """jamps_in_lds: accumulate the jamps in LDS (else registers); jamp_mode for LDS:
+        'atomic' (LDS atomic add in the working precision), 'rmw' (plain LDS read-add-write),
+        'atomic64' (LDS atomic add into an FP64 accumulator), 'auto' (atomic add for the FP64
+        kernel, read-add-write for the FP32 kernel: measured fastest on gfx950, where the
+        FP32 LDS atomic add is far slower than the FP64 one).  remat_ext: recompute external
+        wavefunctions at each use: True, False, 'gluons' or 'spinors'."""
         self.perm_index = {tuple(p): i for i, p in enumerate(self.perms)}
         if jamps_in_lds is None:
             jamps_in_lds = self.nc > 6
         if remat_ext is None:
-            remat_ext = self.nc > 6
+            remat_ext = False
         body = []
         if self.kind == "ee":
             fl = self._emit_ee_body(body)
@@ -280,12 +295,18 @@ class Process:
         lines.append("#pragma unroll")
         lines.append("    for (int i = 0; i < NPAR; ++i) lam[i] = hel[h * NPAR + i];")
         if jamps_in_lds:
-            lines.append("    // jamps accumulate in LDS (one private slot per lane, LDS atomic add)")
-            lines.append("    __shared__ R Jl[2 * NC * 64];")
+            acc = "double" if jamp_mode == "atomic64" else "R"
+            lines.append(f"    // jamps accumulate in LDS, one private slot per lane ({jamp_mode})")
+            lines.append(f"    __shared__ {acc} Jl[2 * NC * 64];")
             lines.append("#pragma unroll")
-            lines.append("    for (int s = 0; s < 2 * NC; ++s) Jl[s * 64 + lane] = (R)0;")
-            lines.append("#define JADD(s, ri, v) lds_add(&Jl[(2 * (s) + (ri)) * 64 + lane], (v))")
-            lines.append("#define JGET(s, ri) Jl[(2 * (s) + (ri)) * 64 + lane]")
+            lines.append(f"    for (int s = 0; s < 2 * NC; ++s) Jl[s * 64 + lane] = ({acc})0;")
+            if jamp_mode == "rmw":
+                lines.append("#define JADD(s, ri, v) (Jl[(2 * (s) + (ri)) * 64 + lane] += (v))")
+            elif jamp_mode == "auto":
+                lines.append("#define JADD(s, ri, v) jamp_add<R>(&Jl[(2 * (s) + (ri)) * 64 + lane], (v))")
+            else:
+                lines.append(f"#define JADD(s, ri, v) lds_add<{acc}>(&Jl[(2 * (s) + (ri)) * 64 + lane], ({acc})(v))")
+            lines.append("#define JGET(s, ri) ((R)Jl[(2 * (s) + (ri)) * 64 + lane])")
         else:
             lines.append("    R Jr[2 * NC];")
             lines.append("#pragma unroll")

@@ -76,6 +76,8 @@ typedef struct {
     int n_par, n_diagrams, n_amplitudes, n_colors, n_hel, n_good_hel, precision;
     double avg_factor, sym_factor;
     double flops_amp_lane;     /* algorithmic flops of the amplitude kernel per (event, helicity) */
+    double flops_amp_exec_lane;/* flops it executes (above when segment kernels recompute currents) */
+    int n_partial_slots;       /* partial jamp slots per (event, helicity) (0: jamps written directly) */
     double flops_colour_lane;  /* algorithmic flops of the colour sum per (event, helicity) */
     int64_t bytes_resident;    /* device bytes held by the handle (tables) */
     int64_t bytes_per_event_scratch; /* jamp scratch per event (per stream in use) */

@@ -24,7 +24,8 @@ class MeInfo(ctypes.Structure):
     _fields_ = [("n_par", ctypes.c_int), ("n_diagrams", ctypes.c_int), ("n_amplitudes", ctypes.c_int),
                 ("n_colors", ctypes.c_int), ("n_hel", ctypes.c_int), ("n_good_hel", ctypes.c_int),
                 ("precision", ctypes.c_int), ("avg_factor", ctypes.c_double), ("sym_factor", ctypes.c_double),
-                ("flops_amp_lane", ctypes.c_double), ("flops_colour_lane", ctypes.c_double),
+                ("flops_amp_lane", ctypes.c_double), ("flops_amp_exec_lane", ctypes.c_double),
+                ("n_partial_slots", ctypes.c_int), ("flops_colour_lane", ctypes.c_double),
                 ("bytes_resident", ctypes.c_int64), ("bytes_per_event_scratch", ctypes.c_int64),
                 ("chunk_events", ctypes.c_int64)]
 

@@ -43,6 +43,9 @@ def build(verbose=True, jobs=None, names=None):
     generate(names)
     srcs = [os.path.join(CSRC, "me_abi.cpp")]
     srcs += [os.path.join(GEN, f"proc_{n}.hip") for n in SUPPORTED]
+    # segment kernels of the large processes live in files of their own
+    srcs += sorted(os.path.join(GEN, f) for f in os.listdir(GEN)
+                   if f.endswith(".hip") and "_amp_seg" in f and f.split("_amp_seg")[0][5:] in SUPPORTED)
     objs = [os.path.join(BUILD, os.path.basename(s) + ".o") for s in srcs]
     # the biggest sources first
     order = sorted(range(len(srcs)), key=lambda i: -os.path.getsize(srcs[i]))

@@ -45,7 +45,8 @@ struct Scratch {
 };
 
 constexpr double PI = 3.141592653589793238462643383279502884;
-constexpr size_t SCRATCH_CAP = size_t(1) << 30;  // jamp scratch per stream
+constexpr size_t SCRATCH_MIN = size_t(1) << 30;   // jamp scratch per stream: at least 1 GiB,
+constexpr int64_t SCRATCH_EVENTS = 4096;          // room for 4096 events, at most 1/8 of the device
 constexpr int PREPASS_EVENTS = 1024;
 constexpr uint64_t PREPASS_SEED = 0x5EED;
 constexpr double PREPASS_THRESHOLD = 1e-20;
@@ -77,6 +78,7 @@ struct me_handle {
     size_t bytes_resident = 0;
     int64_t chunk = 0;
     size_t bytes_per_event = 0;
+    size_t scratch_cap = 0;
     std::mutex mu;
     std::unordered_map<hipStream_t, Scratch> scratch;
     // optional launch timing: HIP events recorded around every kernel launch on its stream
@@ -270,7 +272,9 @@ int helicity_prepass(me_handle* h, hipStream_t st)
     const double sqrt_s = P->coupling ? 1500.0 : 500.0;
     signed char* d_all = nullptr;
     double *d_mom = nullptr, *d_out = nullptr, *d_hel = nullptr, *d_jamp = nullptr;
-    const size_t jbytes = (size_t)nhel * 2 * P->nc * n * sizeof(double);
+    const size_t per_event = (size_t)nhel * 2 * (P->nc + P->nslot) * sizeof(double);
+    const int64_t pchunk = std::min<int64_t>(n, std::max<int64_t>(64, (int64_t)((size_t(512) << 20) / per_event) / 64 * 64));
+    const size_t jbytes = per_event * pchunk;
     int rc = ME_OK;
     if (hipMalloc(&d_all, all.size()) != hipSuccess || hipMalloc(&d_mom, n * npar * 4 * sizeof(double)) != hipSuccess ||
         hipMalloc(&d_out, n * sizeof(double)) != hipSuccess ||
@@ -282,7 +286,7 @@ int helicity_prepass(me_handle* h, hipStream_t st)
         rc = fail(ME_EHIP, "upload of the helicity table failed");
     if (rc == ME_OK && rambo(h, PREPASS_SEED, std::max(sqrt_s, 2.0 * final_mass_sum(h) + 1.0), 0, n, d_mom, st) != hipSuccess)
         rc = fail(ME_EHIP, "pre-pass RAMBO launch failed");
-    if (rc == ME_OK) rc = run_chunks(h, true, d_all, nhel, n, d_mom, n, d_out, d_hel, d_jamp, st);
+    if (rc == ME_OK) rc = run_chunks(h, true, d_all, nhel, pchunk, d_mom, n, d_out, d_hel, d_jamp, st);
     if (rc == ME_OK) {
         if (hipMemcpyAsync(out.data(), d_out, n * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipMemcpyAsync(hel.data(), d_hel, hel.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -362,8 +366,11 @@ me_handle* me_create(const char* process, const double* masses, int n_masses, co
         return nullptr;
     }
     const size_t rsize = (precision == ME_FP64) ? sizeof(double) : sizeof(float);
-    h->bytes_per_event = (size_t)h->n_good * 2 * P->nc * rsize;
-    int64_t chunk = (int64_t)(SCRATCH_CAP / h->bytes_per_event) / 64 * 64;
+    h->bytes_per_event = (size_t)h->n_good * 2 * (P->nc + P->nslot) * rsize;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) total_b = size_t(64) << 30;
+    h->scratch_cap = std::max(SCRATCH_MIN, std::min<size_t>(SCRATCH_EVENTS * h->bytes_per_event, total_b / 8));
+    int64_t chunk = (int64_t)(h->scratch_cap / h->bytes_per_event) / 64 * 64;
     h->chunk = std::max<int64_t>(64, chunk);
     return h;
 }
@@ -384,6 +391,8 @@ int me_info(const me_handle* h, me_info_t* out)
     out->avg_factor = P->avg;
     out->sym_factor = P->sym;
     out->flops_amp_lane = P->flops_lane;
+    out->flops_amp_exec_lane = P->flops_exec_lane;
+    out->n_partial_slots = P->nslot;
     out->flops_colour_lane = 4.0 * P->nc * P->nc + 4.0 * P->nc + 1.0;
     out->bytes_resident = (int64_t)h->bytes_resident;
     out->bytes_per_event_scratch = (int64_t)h->bytes_per_event;
@@ -427,7 +436,9 @@ int me_sigma_hel(me_handle* h, const double* momenta, int64_t n_evt, double* out
         return fail(ME_EINVAL, "momenta and outputs must be device pointers");
     if (reinterpret_cast<uintptr_t>(momenta) % 16 != 0) return fail(ME_EINVAL, "momenta must be 16-byte aligned");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const int64_t chunk = std::min<int64_t>(h->chunk, (n_evt + 63) / 64 * 64);
+    // equal chunks no larger than the scratch cap allows
+    const int64_t n_chunks = (n_evt + h->chunk - 1) / h->chunk;
+    const int64_t chunk = ((n_evt + n_chunks - 1) / n_chunks + 63) / 64 * 64;
     const size_t need = (size_t)chunk * h->bytes_per_event;
     void* jamp = nullptr;
     {
@@ -440,7 +451,7 @@ int me_sigma_hel(me_handle* h, const double* momenta, int64_t n_evt, double* out
                 s.ptr = nullptr;
                 s.bytes = 0;
             }
-            size_t want = std::max(need, std::min<size_t>(SCRATCH_CAP, 2 * s.bytes));
+            size_t want = std::max(need, std::min<size_t>(h->scratch_cap, 2 * s.bytes));
             if (hipMalloc(&s.ptr, want) != hipSuccess) {
                 (void)hipGetLastError();
                 return fail(ME_ENOMEM, "hipMalloc of the jamp scratch failed");

@@ -25,6 +25,8 @@ struct ProcessDesc {
     int n_diagrams;            // Feynman diagrams
     int n_amplitudes;          // vertex contractions (four-gluon vertices count 3)
     double flops_lane;         // algorithmic flops of the amplitude kernel per (event, helicity)
+    double flops_exec_lane;    // flops it executes (more when segments recompute currents)
+    int nslot;                 // partial jamp slots per (event, helicity); 0: jamps written directly
     amp_launch_f64 launch_f64;
     amp_launch_f32 launch_f32;
 };

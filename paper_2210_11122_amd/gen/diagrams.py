@@ -353,3 +353,132 @@ def schedule(plan, remat_ext=False):
             pending[d] -= 1
         order.append(amps[best])
     return order
+
+
+def schedule_window(amps, nodes, jamp_sets, beta, window):
+    """Greedy order like `schedule`, with an extra cost of `beta` per jamp of the candidate
+    amplitude that is not in an LRU window of `window` jamps (jamp locality: fewer window
+    evictions).  amps: [(diagram index, option, deps)]; jamp_sets[diagram] = jamp indices."""
+    import collections
+    consumers = {k: 0 for k in nodes}
+    for k in nodes:
+        for d in node_deps(k):
+            consumers[d] += 1
+    for _, _, deps in amps:
+        for d in deps:
+            consumers[d] += 1
+    pending = dict(consumers)
+    computed = set()
+    win = collections.OrderedDict()
+
+    def missing(deps):
+        out, seen = [], set()
+
+        def rec(k):
+            if k in computed or k in seen:
+                return
+            for d in node_deps(k):
+                rec(d)
+            seen.add(k)
+            out.append(k)
+        for d in deps:
+            rec(d)
+        return out
+
+    def score(i):
+        deps = amps[i][2]
+        new = missing(deps)
+        add = sum(node_size(k) for k in new)
+        dec = {}
+        for k in new:
+            for d in node_deps(k):
+                dec[d] = dec.get(d, 0) + 1
+        for d in deps:
+            dec[d] = dec.get(d, 0) + 1
+        freed = 0
+        newset = set(new)
+        for d, c in dec.items():
+            total = pending[d] + (consumers[d] if d in newset else 0)
+            if c >= total:
+                freed += node_size(d)
+        miss = sum(1 for j in jamp_sets[amps[i][0]] if j not in win)
+        return (add - freed + beta * miss, add)
+
+    remaining = list(range(len(amps)))
+    order = []
+    while remaining:
+        best = min(remaining, key=score)
+        remaining.remove(best)
+        deps = amps[best][2]
+        for k in missing(deps):
+            computed.add(k)
+            for d in node_deps(k):
+                pending[d] -= 1
+        for d in deps:
+            pending[d] -= 1
+        for j in sorted(jamp_sets[amps[best][0]]):
+            if j in win:
+                win.move_to_end(j)
+            else:
+                if len(win) >= window:
+                    win.popitem(last=False)
+                win[j] = 1
+        order.append(amps[best])
+    return order
+
+
+def closure(deps):
+    need, st = set(), list(deps)
+    while st:
+        x = st.pop()
+        if x in need:
+            continue
+        need.add(x)
+        st.extend(node_deps(x))
+    return need
+
+
+def segment_plan(plan, jamp_sets, n_segments, beta, window):
+    """Cut the jamp-aware order into n_segments contiguous pieces (one kernel each, which
+    recomputes the currents it needs) and reorder each piece the same way."""
+    amps = plan.amplitudes()
+    order = schedule_window(amps, plan.nodes(), jamp_sets, beta, window)
+    n = len(order)
+    segs = []
+    for k in range(n_segments):
+        piece = order[k * n // n_segments:(k + 1) * n // n_segments]
+        need = closure([d for _, _, deps in piece for d in deps])
+        segs.append(schedule_window(piece, need, jamp_sets, beta, window))
+    return segs
+
+
+def window_program(order, jamp_sets, window):
+    """Static LRU allocation of jamps to `window` slots along `order`.  Returns, per
+    amplitude, [(jamp, slot, flush)] where flush is None or (slot, partial index, jamp)
+    to write out before the slot is reused, plus the final flushes and the jamp of every
+    partial slot."""
+    import collections
+    win = collections.OrderedDict()   # jamp -> slot
+    free = list(range(window))[::-1]
+    partial_jamp = []
+    steps = []
+    for di, _, _ in order:
+        ops = []
+        for j in sorted(jamp_sets[di]):
+            flush = None
+            if j in win:
+                win.move_to_end(j)
+            else:
+                if not free:
+                    jj, s = win.popitem(last=False)
+                    flush = (s, len(partial_jamp), jj)
+                    partial_jamp.append(jj)
+                    free.append(s)
+                win[j] = free.pop()
+            ops.append((j, win[j], flush))
+        steps.append(ops)
+    final = []
+    for jj, s in win.items():
+        final.append((s, len(partial_jamp), jj))
+        partial_jamp.append(jj)
+    return steps, final, partial_jamp

@@ -26,6 +26,8 @@ FLOPS = {
 }
 
 QCD_PROCESSES = {"gg_tt": 2, "gg_ttg": 3, "gg_ttgg": 4, "gg_ttggg": 5}
+# name -> (segment kernels, LDS jamp-window slots, weight of window misses in the schedule)
+SEGMENTS = {"gg_ttggg": (8, 24, 1.0)}
 ALL_PROCESSES = ["ee_mumu", "gg_tt", "gg_ttg", "gg_ttgg", "gg_ttggg", "gg_gg"]
 
 
@@ -52,6 +54,10 @@ class Process:
             self.avg = 256
             self.sym = {2: 1, 3: 1, 4: 2, 5: 6}[n]
             self.coupling = "alpha_s"
+        # processes too large for one kernel: the diagram program is cut into segments
+        # (one kernel each) and the jamps go through a window of LDS slots, written out as
+        # partial sums
+        self.segments = SEGMENTS.get(name)
         self._build()
 
     # -----------------------------------------------------------------------------------
@@ -92,7 +98,7 @@ class Process:
         p = self.gpar[i]
         return f"p[{p}]" if p < 2 else f"(-p[{p}])"
 
-    def _emit_qcd_body(self, out, remat_ext):
+    def _emit_qcd_body(self, out, remat_ext, order=None, steps=None, final=None):
         """Emit the diagram program.  Momentum sums are written inline from fresh LDS reads
         at every use (so no four-momentum stays live in registers); with remat_ext the
         external wavefunctions are recomputed at every use instead of being kept live.
@@ -191,7 +197,9 @@ class Process:
             names[key] = nm
             return nm
 
-        for di, opt, deps in D.schedule(self.plan, remat_ext=remat_ext):
+        if order is None:
+            order = D.schedule(self.plan, remat_ext=remat_ext)
+        for ai, (di, opt, deps) in enumerate(order):
             d = self.diagrams[di]
             kind, j = opt
             if kind == "FFV":
@@ -214,9 +222,20 @@ class Process:
                 else:
                     out.append(f"    a = amp_vvvv<R, {t[1]}>({wx}, {ws[0]}, {ws[1]}, {ws[2]}, gs);")
                     flops[0] += FLOPS["amp_vvvv"]
-            for seq, c in sorted(self.jcoef[di].items()):
-                out.append(self._jamp_update(self.perm_index[seq], c))
-                flops[0] += FLOPS["jamp"]
+            if steps is None:
+                for seq, c in sorted(self.jcoef[di].items()):
+                    out.append(self._jamp_update(self.perm_index[seq], c))
+                    flops[0] += FLOPS["jamp"]
+            else:
+                coef = {self.perm_index[seq]: c for seq, c in self.jcoef[di].items()}
+                for j, slot, flush in steps[ai]:
+                    if flush is not None:
+                        out.append(f"    JFLUSH({flush[0]}, {flush[1]});")
+                    out.append(self._jamp_update(slot, coef[j]))
+                    flops[0] += FLOPS["jamp"]
+        if final:
+            for slot, pidx, _ in final:
+                out.append(f"    JFLUSH({slot}, {pidx});")
         return flops[0]
 
     @staticmethod
@@ -258,108 +277,228 @@ class Process:
             jamps_in_lds = self.nc > 6
         if remat_ext is None:
             remat_ext = False
-        body = []
-        if self.kind == "ee":
-            fl = self._emit_ee_body(body)
-        else:
-            fl = self._emit_qcd_body(body, remat_ext)
-        self.flops_lane = fl
         nc = self.nc
         nm = self.name
+        kernels = []      # (kernel name, body lines, jamp slots in LDS, output mode)
+        self.nslot = 0
+        if self.kind == "ee":
+            body = []
+            fl = self._emit_ee_body(body)
+            kernels.append(("amp_kernel", body, nc, "jamps"))
+            self.flops_exec = fl
+        elif not self.segments:
+            body = []
+            fl = self._emit_qcd_body(body, remat_ext)
+            kernels.append(("amp_kernel", body, nc, "jamps"))
+            self.flops_exec = fl
+        else:
+            n_seg, window, beta = self.segments
+            jsets = [set(self.perm_index[q] for q in self.jcoef[i]) for i in range(len(self.diagrams))]
+            # algorithmic count: every node once, in any order
+            fl = self._emit_qcd_body([], remat_ext, order=self.plan.amplitudes())
+            segs = D.segment_plan(self.plan, jsets, n_seg, beta, window)
+            self.flops_exec = 0
+            partial_jamp = []
+            for k, order in enumerate(segs):
+                steps, final, pj = D.window_program(order, jsets, window)
+                base = len(partial_jamp)
+                steps = [[(j, sl, None if f is None else (f[0], f[1] + base, f[2])) for j, sl, f in st]
+                         for st in steps]
+                final = [(sl, pi + base, j) for sl, pi, j in final]
+                partial_jamp += pj
+                body = []
+                self.flops_exec += self._emit_qcd_body(body, remat_ext, order=order, steps=steps, final=final)
+                kernels.append((f"amp_seg{k}", body, window, "slots"))
+            self.nslot = len(partial_jamp)
+            self.partial_jamp = partial_jamp
+        self.flops_lane = fl
         cn = ", ".join(str(x) for row in self.cnum for x in row)
         masses = ", ".join("1" if m == "m" else "0" for m in self.final_masses)
         perm_flat = ", ".join(str(x) for p in self.perms for x in p) or "0"
-        lines = []
-        lines.append(f"// Generated by paper_2210_11122_amd.gen for the process {nm}; do not edit.")
-        lines.append(f"// {self.n_diagrams} Feynman diagrams ({self.n_amplitudes} vertex contractions), "
-                     f"{nc} colour flows, {1 << self.npar} helicity combinations.")
-        lines.append('#include "../helas.hpp"')
-        lines.append('#include "../process.hpp"')
-        lines.append("namespace me {")
-        lines.append(f"namespace proc_{nm} {{")
-        lines.append(f"constexpr int NPAR = {self.npar};")
-        lines.append(f"constexpr int NC = {nc};")
-        lines.append("template <class R>")
-        lines.append("__global__ __launch_bounds__(64) void amp_kernel(const double* __restrict__ mom, int64_t n_evt, "
-                     "int64_t ld, const signed char* __restrict__ hel, int n_good, double mt, double gs, "
-                     "R* __restrict__ jamp)")
-        lines.append("{")
-        lines.append("    __shared__ double lds[4 * NPAR * 64];")
-        lines.append("    const int lane = threadIdx.x;")
-        lines.append("    const int64_t w = xcd_remap(blockIdx.x, gridDim.x);")
-        lines.append("    const int64_t e0 = (w / n_good) * 64;")
-        lines.append("    const int h = (int)(w % n_good);")
-        lines.append("    stage_momenta<NPAR>(mom, n_evt, e0, lds, lane);")
-        lines.append("#define PM(i) lds_p4(lds, i, lane)")
-        lines.append("    int lam[NPAR];")
-        lines.append("#pragma unroll")
-        lines.append("    for (int i = 0; i < NPAR; ++i) lam[i] = hel[h * NPAR + i];")
-        if jamps_in_lds:
-            acc = "double" if jamp_mode == "atomic64" else "R"
-            lines.append(f"    // jamps accumulate in LDS, one private slot per lane ({jamp_mode})")
-            lines.append(f"    __shared__ {acc} Jl[2 * NC * 64];")
-            lines.append("#pragma unroll")
-            lines.append(f"    for (int s = 0; s < 2 * NC; ++s) Jl[s * 64 + lane] = ({acc})0;")
-            if jamp_mode == "rmw":
-                lines.append("#define JADD(s, ri, v) (Jl[(2 * (s) + (ri)) * 64 + lane] += (v))")
-            elif jamp_mode == "auto":
-                lines.append("#define JADD(s, ri, v) jamp_add<R>(&Jl[(2 * (s) + (ri)) * 64 + lane], (v))")
-            else:
-                lines.append(f"#define JADD(s, ri, v) lds_add<{acc}>(&Jl[(2 * (s) + (ri)) * 64 + lane], ({acc})(v))")
-            lines.append("#define JGET(s, ri) ((R)Jl[(2 * (s) + (ri)) * 64 + lane])")
+        L = []
+        L.append(f"// Generated by paper_2210_11122_amd.gen for the process {nm}; do not edit.")
+        L.append(f"// {self.n_diagrams} Feynman diagrams ({self.n_amplitudes} vertex contractions), "
+                 f"{nc} colour flows, {1 << self.npar} helicity combinations.")
+        if self.segments:
+            L.append(f"// {len(kernels)} segment kernels, {self.segments[1]}-slot LDS jamp window, "
+                     f"{self.nslot} partial jamp slots; executed flops per lane {self.flops_exec} "
+                     f"(algorithmic {fl}).")
+        L.append('#include "../helas.hpp"')
+        L.append('#include "../process.hpp"')
+        L.append("namespace me {")
+        L.append(f"namespace proc_{nm} {{")
+        L.append(f"constexpr int NPAR = {self.npar};")
+        L.append(f"constexpr int NC = {nc};")
+        L.append(f"constexpr int NSLOT = {self.nslot};")
+        self.extra_files = {}
+        if self.segments:
+            # one source file per segment kernel (compiled in parallel); the main file calls
+            # their host-side launchers
+            for kname, body, nwin, mode in kernels:
+                F = [f"// Generated by paper_2210_11122_amd.gen: {nm}, {kname}; do not edit.",
+                     '#include "../helas.hpp"', "namespace me {", f"namespace proc_{nm} {{",
+                     f"constexpr int NPAR = {self.npar};", f"constexpr int NC = {nc};",
+                     f"constexpr int NSLOT = {self.nslot};"]
+                F += self._kernel_text(kname, body, nwin, mode, jamps_in_lds, jamp_mode)
+                for R, tag in (("double", "f64"), ("float", "f32")):
+                    F.append(f"hipError_t {kname}_launch_{tag}(const double* mom, int64_t n_evt, int64_t ld, "
+                             f"const signed char* hel, int n_good, double mt, double gs, {R}* jamp, hipStream_t st, "
+                             "int64_t blocks)")
+                    F.append("{")
+                    F.append(f"    hipLaunchKernelGGL({kname}<{R}>, dim3((unsigned)blocks), dim3(64), 0, st, mom, n_evt, "
+                             "ld, hel, n_good, mt, gs, jamp);")
+                    F.append("    return hipGetLastError();")
+                    F.append("}")
+                F += ["}  // namespace", "}  // namespace me"]
+                self.extra_files[f"proc_{nm}_{kname}.hip"] = "\n".join(F) + "\n"
+                for R, tag in (("double", "f64"), ("float", "f32")):
+                    L.append(f"hipError_t {kname}_launch_{tag}(const double*, int64_t, int64_t, const signed char*, "
+                             f"int, double, double, {R}*, hipStream_t, int64_t);")
         else:
-            lines.append("    R Jr[2 * NC];")
-            lines.append("#pragma unroll")
-            lines.append("    for (int s = 0; s < 2 * NC; ++s) Jr[s] = (R)0;")
-            lines.append("#define JADD(s, ri, v) (Jr[2 * (s) + (ri)] += (v))")
-            lines.append("#define JGET(s, ri) Jr[2 * (s) + (ri)]")
-        lines.append("    cx<R> a;")
-        lines.extend(body)
-        lines.append("    const int64_t e = e0 + lane;")
-        lines.append("    if (e < n_evt) {")
-        lines.append("        R* o = jamp + (int64_t)h * (2 * NC) * ld + e;")
-        lines.append("#pragma unroll")
-        lines.append("        for (int s = 0; s < NC; ++s) {")
-        lines.append("            o[(2 * s) * ld] = JGET(s, 0);")
-        lines.append("            o[(2 * s + 1) * ld] = JGET(s, 1);")
-        lines.append("        }")
-        lines.append("    }")
-        lines.append("#undef PM")
-        lines.append("#undef JADD")
-        lines.append("#undef JGET")
-        lines.append("}")
-        lines.append("")
-        lines.append(f"static const int colour_num[NC * NC] = {{{cn}}};")
-        lines.append(f"static const int final_massive[NPAR - 2] = {{{masses}}};")
-        lines.append(f"static const int orderings[] = {{{perm_flat}}};")
-        lines.append("template <class R>")
-        lines.append("static hipError_t launch(const double* mom, int64_t n_evt, int64_t ld, const signed char* hel, "
-                     "int n_good, double mt, double gs, R* jamp, hipStream_t st)")
-        lines.append("{")
-        lines.append("    int64_t blocks = ((n_evt + 63) / 64) * n_good;")
-        lines.append("    if (blocks == 0) return hipSuccess;")
-        lines.append("    hipLaunchKernelGGL(amp_kernel<R>, dim3((unsigned)blocks), dim3(64), 0, st, mom, n_evt, ld, hel, "
-                     "n_good, mt, gs, jamp);")
-        lines.append("    return hipGetLastError();")
-        lines.append("}")
-        lines.append("}  // namespace")
-        lines.append(f"const ProcessDesc* process_{nm}()")
-        lines.append("{")
-        lines.append("    static const ProcessDesc d = {")
-        lines.append(f'        "{nm}", proc_{nm}::NPAR, proc_{nm}::NC, {1 << self.npar}, '
-                     f"{self.avg}, {self.sym}, {1 if self.coupling == 'alpha_s' else 0},")
-        lines.append(f"        proc_{nm}::colour_num, {self.cden}, proc_{nm}::final_massive, proc_{nm}::orderings,")
-        lines.append(f"        {self.n_diagrams}, {self.n_amplitudes}, {fl}.0,")
-        lines.append(f"        proc_{nm}::launch<double>, proc_{nm}::launch<float>,")
-        lines.append("    };")
-        lines.append("    return &d;")
-        lines.append("}")
-        lines.append("}  // namespace me")
-        return "\n".join(lines) + "\n"
+            for kname, body, nwin, mode in kernels:
+                L += self._kernel_text(kname, body, nwin, mode, jamps_in_lds, jamp_mode)
+        L.append("")
+        L.append(f"static const int colour_num[NC * NC] = {{{cn}}};")
+        L.append(f"static const int final_massive[NPAR - 2] = {{{masses}}};")
+        L.append(f"static const int orderings[] = {{{perm_flat}}};")
+        if self.segments:
+            L += self._reduce_text()
+        L.append("template <class R>")
+        L.append("static hipError_t launch(const double* mom, int64_t n_evt, int64_t ld, const signed char* hel, "
+                 "int n_good, double mt, double gs, R* jamp, hipStream_t st)")
+        L.append("{")
+        L.append("    int64_t blocks = ((n_evt + 63) / 64) * n_good;")
+        L.append("    if (blocks == 0) return hipSuccess;")
+        for kname, _, _, _ in kernels:
+            if self.segments:
+                L.append("    {")
+                L.append(f"        hipError_t e = sizeof(R) == 8 ? {kname}_launch_f64(mom, n_evt, ld, hel, n_good, mt, gs, "
+                         "(double*)jamp, st, blocks)")
+                L.append(f"                                      : {kname}_launch_f32(mom, n_evt, ld, hel, n_good, mt, gs, "
+                         "(float*)jamp, st, blocks);")
+                L.append("        if (e != hipSuccess) return e;")
+                L.append("    }")
+            else:
+                L.append(f"    hipLaunchKernelGGL({kname}<R>, dim3((unsigned)blocks), dim3(64), 0, st, mom, n_evt, ld, hel, "
+                         "n_good, mt, gs, jamp);")
+        if self.segments:
+            L.append("    hipLaunchKernelGGL(reduce_kernel<R>, dim3((unsigned)((n_evt + 255) / 256), (unsigned)n_good), "
+                     "dim3(256), 0, st, jamp, ld, n_good, n_evt);")
+        L.append("    return hipGetLastError();")
+        L.append("}")
+        L.append("}  // namespace")
+        L.append(f"const ProcessDesc* process_{nm}()")
+        L.append("{")
+        L.append("    static const ProcessDesc d = {")
+        L.append(f'        "{nm}", proc_{nm}::NPAR, proc_{nm}::NC, {1 << self.npar}, '
+                 f"{self.avg}, {self.sym}, {1 if self.coupling == 'alpha_s' else 0},")
+        L.append(f"        proc_{nm}::colour_num, {self.cden}, proc_{nm}::final_massive, proc_{nm}::orderings,")
+        L.append(f"        {self.n_diagrams}, {self.n_amplitudes}, {fl}.0, {self.flops_exec}.0, proc_{nm}::NSLOT,")
+        L.append(f"        proc_{nm}::launch<double>, proc_{nm}::launch<float>,")
+        L.append("    };")
+        L.append("    return &d;")
+        L.append("}")
+        L.append("}  // namespace me")
+        return "\n".join(L) + "\n"
+
+    def _kernel_text(self, kname, body, nwin, mode, jamps_in_lds, jamp_mode):
+        """one amplitude kernel: momenta staging, helicity signs, jamp storage, body, output.
+        mode 'jamps': the NC jamps are written at the end, layout [h][2c + re/im][column];
+        mode 'slots': the body flushes window slots to partial slots (JFLUSH), layout
+        [h][2s + re/im][column] after the jamp region."""
+        L = []
+        L.append("template <class R>")
+        L.append(f"__global__ __launch_bounds__(64) void {kname}(const double* __restrict__ mom, int64_t n_evt, "
+                 "int64_t ld, const signed char* __restrict__ hel, int n_good, double mt, double gs, "
+                 "R* __restrict__ jamp)")
+        L.append("{")
+        L.append("    __shared__ double lds[4 * NPAR * 64];")
+        L.append("    const int lane = threadIdx.x;")
+        L.append("    const int64_t w = xcd_remap(blockIdx.x, gridDim.x);")
+        L.append("    const int64_t e0 = (w / n_good) * 64;")
+        L.append("    const int h = (int)(w % n_good);")
+        L.append("    const int64_t e = e0 + lane;  // < ld: ld is a multiple of 64 covering the grid")
+        L.append("    stage_momenta<NPAR>(mom, n_evt, e0, lds, lane);")
+        L.append("#define PM(i) lds_p4(lds, i, lane)")
+        L.append("    int lam[NPAR];")
+        L.append("#pragma unroll")
+        L.append("    for (int i = 0; i < NPAR; ++i) lam[i] = hel[h * NPAR + i];")
+        L.append(f"    constexpr int NW = {nwin};")
+        if jamps_in_lds or mode == "slots":
+            acc = "double" if jamp_mode == "atomic64" else "R"
+            L.append(f"    // jamps accumulate in LDS, one private slot per lane ({jamp_mode})")
+            L.append(f"    __shared__ {acc} Jl[2 * NW * 64];")
+            L.append("#pragma unroll")
+            L.append(f"    for (int s = 0; s < 2 * NW; ++s) Jl[s * 64 + lane] = ({acc})0;")
+            if jamp_mode == "rmw":
+                L.append("#define JADD(s, ri, v) (Jl[(2 * (s) + (ri)) * 64 + lane] += (v))")
+            elif jamp_mode == "auto":
+                L.append("#define JADD(s, ri, v) jamp_add<R>(&Jl[(2 * (s) + (ri)) * 64 + lane], (v))")
+            else:
+                L.append(f"#define JADD(s, ri, v) lds_add<{acc}>(&Jl[(2 * (s) + (ri)) * 64 + lane], ({acc})(v))")
+            L.append("#define JGET(s, ri) ((R)Jl[(2 * (s) + (ri)) * 64 + lane])")
+            L.append(f"#define JZERO(s, ri) (Jl[(2 * (s) + (ri)) * 64 + lane] = ({acc})0)")
+        else:
+            L.append("    R Jr[2 * NW];")
+            L.append("#pragma unroll")
+            L.append("    for (int s = 0; s < 2 * NW; ++s) Jr[s] = (R)0;")
+            L.append("#define JADD(s, ri, v) (Jr[2 * (s) + (ri)] += (v))")
+            L.append("#define JGET(s, ri) Jr[2 * (s) + (ri)]")
+        if mode == "slots":
+            L.append("    R* const po = jamp + (int64_t)n_good * (2 * NC) * ld + (int64_t)h * (2 * NSLOT) * ld + e;")
+            L.append("#define JFLUSH(s, p) do { po[(int64_t)(2 * (p)) * ld] = JGET(s, 0); "
+                     "po[(int64_t)(2 * (p) + 1) * ld] = JGET(s, 1); JZERO(s, 0); JZERO(s, 1); } while (0)")
+        L.append("    cx<R> a;")
+        L.extend(body)
+        if mode == "jamps":
+            L.append("    if (e < n_evt) {")
+            L.append("        R* o = jamp + (int64_t)h * (2 * NC) * ld + e;")
+            L.append("#pragma unroll")
+            L.append("        for (int s = 0; s < NC; ++s) {")
+            L.append("            o[(2 * s) * ld] = JGET(s, 0);")
+            L.append("            o[(2 * s + 1) * ld] = JGET(s, 1);")
+            L.append("        }")
+            L.append("    }")
+        for m in ("PM", "JADD", "JGET", "JZERO", "JFLUSH"):
+            L.append(f"#undef {m}")
+        L.append("}")
+        return L
+
+    def _reduce_text(self):
+        """the partial slots of each jamp, summed in flush order, into the jamp layout"""
+        offs = [0]
+        lst = []
+        for c in range(self.nc):
+            lst += [p for p, j in enumerate(self.partial_jamp) if j == c]
+            offs.append(len(lst))
+        L = []
+        L.append(f"__constant__ int slot_offset[NC + 1] = {{{', '.join(map(str, offs))}}};")
+        L.append(f"__constant__ int slot_list[NSLOT] = {{{', '.join(map(str, lst))}}};")
+        L.append("template <class R>")
+        L.append("__global__ __launch_bounds__(256) void reduce_kernel(R* __restrict__ jamp, int64_t ld, int n_good, "
+                 "int64_t n_evt)")
+        L.append("{")
+        L.append("    const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;")
+        L.append("    const int h = blockIdx.y;")
+        L.append("    if (col >= n_evt) return;")
+        L.append("    const R* P = jamp + (int64_t)n_good * (2 * NC) * ld + (int64_t)h * (2 * NSLOT) * ld + col;")
+        L.append("    R* J = jamp + (int64_t)h * (2 * NC) * ld + col;")
+        L.append("    for (int c = 0; c < NC; ++c) {")
+        L.append("        R re = (R)0, im = (R)0;")
+        L.append("        for (int k = slot_offset[c]; k < slot_offset[c + 1]; ++k) {")
+        L.append("            const int s = slot_list[k];")
+        L.append("            re += P[(int64_t)(2 * s) * ld];")
+        L.append("            im += P[(int64_t)(2 * s + 1) * ld];")
+        L.append("        }")
+        L.append("        J[(int64_t)(2 * c) * ld] = re;")
+        L.append("        J[(int64_t)(2 * c + 1) * ld] = im;")
+        L.append("    }")
+        L.append("}")
+        return L
 
 
 # processes whose diagram program is not emitted yet: the library reports them as unknown
-NOT_EMITTED = {"gg_ttggg"}
+NOT_EMITTED = set()
 
 
 def stub_source(nm):
@@ -382,6 +521,11 @@ def generate(outdir, names=None):
             continue
         P = Process(nm)
         src = P.source()
+        for fname, fsrc in getattr(P, "extra_files", {}).items():
+            fpath = os.path.join(outdir, fname)
+            if not os.path.exists(fpath) or open(fpath).read() != fsrc:
+                with open(fpath, "w") as f:
+                    f.write(fsrc)
         path = os.path.join(outdir, f"proc_{nm}.hip")
         old = open(path).read() if os.path.exists(path) else None
         if old != src:

@@ -1,0 +1,188 @@
+"""CPU tests of the process generator (diagram enumeration, colour algebra, evaluation
+plan, jamp window) against independent definitions."""
+import itertools
+import math
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2210_11122_amd.gen import colour, diagrams as D, emit
+
+# Gell-Mann matrices, written out here (not taken from the generator)
+_L = np.zeros((8, 3, 3), complex)
+_L[0][0, 1] = _L[0][1, 0] = 1
+_L[1][0, 1], _L[1][1, 0] = -1j, 1j
+_L[2][0, 0], _L[2][1, 1] = 1, -1
+_L[3][0, 2] = _L[3][2, 0] = 1
+_L[4][0, 2], _L[4][2, 0] = -1j, 1j
+_L[5][1, 2] = _L[5][2, 1] = 1
+_L[6][1, 2], _L[6][2, 1] = -1j, 1j
+_L[7] = np.diag([1, 1, -2]) / math.sqrt(3)
+T = _L / 2
+
+
+@pytest.mark.parametrize("n,count,amps", [(2, 3, 3), (3, 16, 18), (4, 123, 159), (5, 1240, 1890)])
+def test_diagram_counts(n, count, amps):
+    ds = D.quark_line_diagrams(n)
+    assert len(ds) == amps
+    assert sum(1 for d in ds if D.is_canonical_structure(d)) == count
+    for d in ds:
+        assert sorted(g for t in d for g in D.leaves(t)) == list(range(n))
+
+
+def test_gluon_trees():
+    # trees with 1..4 leaves under a root leg: 1, 1, 4 (3 + one quartic), 25
+    for k, want in [(1, 1), (2, 1), (3, 4), (4, 25)]:
+        ts = D.trees(tuple(range(k)))
+        assert sum(1 for t in ts if D.is_canonical_structure((t,))) == want
+    # gg -> gg: s, t, u and the contact diagram
+    assert sum(1 for t in D.trees((0, 1, 2)) if D.is_canonical_structure((t,))) == 4
+
+
+@pytest.mark.parametrize("proc,n", [("gg_tt", 2), ("gg_ttg", 3), ("gg_ttgg", 4), ("gg_ttggg", 5)])
+def test_colour_matrix_exact_vs_oracle(proc, n):
+    perms, C = colour.colour_matrix_quark_line(n)
+    assert [tuple(p) for p in perms] == oracle.orderings(proc)
+    Co = oracle.colour_matrix(proc)
+    assert np.allclose(np.array(C, dtype=float), Co, atol=1e-12)
+
+
+def test_single_trace_matrix_exact_vs_oracle():
+    perms, C = colour.colour_matrix_single_trace(4)
+    assert [tuple(p) for p in perms] == oracle.orderings("gg_gg")
+    assert np.allclose(np.array(C, dtype=float), oracle.colour_matrix("gg_gg"), atol=1e-13)
+
+
+@pytest.mark.parametrize("name", ["gg_tt", "gg_ttg", "gg_ttgg", "gg_ttggg", "gg_gg"])
+def test_colour_numerators_exact_in_fp16(name):
+    P = emit.Process(name)
+    h = np.array(P.cnum, dtype=np.float64)
+    assert np.array_equal(h.astype(np.float16).astype(np.float64), h)
+
+
+def explicit_tree(t, col, f):
+    """adjoint colour vector of a subtree for explicit external colours"""
+    if t[0] == "L":
+        v = np.zeros(8)
+        v[col[t[1]]] = 1
+        return v
+    if t[0] == "V3":
+        A, B = explicit_tree(t[1], col, f), explicit_tree(t[2], col, f)
+        return np.einsum("xab,a,b->x", f, A, B)
+    k = t[1]
+    A, B, C = (explicit_tree(c, col, f) for c in t[2:])
+    if k == 0:
+        return np.einsum("xae,bce,a,b,c->x", f, f, A, B, C)
+    if k == 1:
+        return np.einsum("xbe,ace,a,b,c->x", f, f, A, B, C)
+    return np.einsum("xce,abe,a,b,c->x", f, f, A, B, C)
+
+
+@pytest.mark.parametrize("n,n_diag", [(2, 3), (3, 18), (4, 40), (5, 60)])
+def test_diagram_colour_decomposition_explicit(n, n_diag):
+    """every checked diagram: explicit f/t contraction == sum_s c_s (T^s)_ij"""
+    f = oracle.fabc()
+    rng = np.random.default_rng(n)
+    ds = D.quark_line_diagrams(n)
+    idx = rng.choice(len(ds), size=min(n_diag, len(ds)), replace=False)
+    for i in idx:
+        d = ds[int(i)]
+        dec = D.diagram_colour(d, "qline")
+        for _ in range(3):
+            col = rng.integers(0, 8, n)
+            M = np.eye(3, dtype=complex)
+            for t in d:
+                M = M @ np.einsum("x,xij->ij", explicit_tree(t, col, f), T)
+            S = np.zeros((3, 3), complex)
+            for seq, c in dec.items():
+                P = np.eye(3, dtype=complex)
+                for g in seq:
+                    P = P @ T[col[g]]
+                S += complex(c.re, c.im) * P
+            assert np.allclose(M, S, atol=1e-12)
+
+
+def test_pure_gluon_decomposition_explicit():
+    f = oracle.fabc()
+    rng = np.random.default_rng(3)
+    for t in D.trees((0, 1, 2)):
+        dec = D.diagram_colour((t,), "gluon")
+        for _ in range(4):
+            col = rng.integers(0, 8, 4)
+            X = explicit_tree(t, col, f)[col[3]]
+            S = 0
+            for seq, c in dec.items():
+                P = T[col[3]].copy()
+                for g in seq:
+                    P = P @ T[col[g]]
+                S += complex(c.re, c.im) * np.trace(P)
+            assert abs(X - S) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["gg_tt", "gg_ttg", "gg_ttgg"])
+def test_every_diagram_evaluated_once(name):
+    P = emit.Process(name)
+    src = P.source()
+    assert len(re.findall(r"^\s+a = amp_", src, re.M)) == P.n_amplitudes
+    # every node of the plan computed exactly once
+    names = re.findall(r"const W4<R> (w\d+) =", src)
+    assert len(names) == len(set(names)) == len(P.plan.nodes())
+
+
+def test_plan_covers_every_diagram_with_its_own_subdiagrams():
+    """each amplitude's dependencies reproduce exactly the diagram's blocks"""
+    ds = D.quark_line_diagrams(4)
+    plan = D.Plan(ds, "qline")
+    for di, opt, deps in plan.amplitudes():
+        d = ds[di]
+        kind, j = opt
+        leaves = set()
+        for k in D.closure(deps):
+            if k[0] == "EXT_G":
+                leaves.add(k[1])
+        assert leaves == set(range(4))
+        if kind == "FFV":
+            assert deps[2] == D.wf_key(d[j])
+
+
+def test_window_program_reproduces_direct_accumulation():
+    """replay the gg_ttggg jamp window (LRU slots, flushes, partial slots, reduction) with
+    random amplitudes and compare with direct accumulation of every diagram"""
+    P = emit.Process("gg_ttggg")
+    P.source()  # builds the segments and the partial-slot map
+    perm_index = {tuple(p): i for i, p in enumerate(P.perms)}
+    jsets = [set(perm_index[q] for q in P.jcoef[i]) for i in range(len(P.diagrams))]
+    n_seg, window, beta = P.segments
+    segs = D.segment_plan(P.plan, jsets, n_seg, beta, window)
+    rng = np.random.default_rng(0)
+    amp = rng.normal(size=len(P.diagrams)) + 1j * rng.normal(size=len(P.diagrams))
+    direct = np.zeros(P.nc, complex)
+    for di in range(len(P.diagrams)):
+        for q, c in P.jcoef[di].items():
+            direct[perm_index[q]] += complex(c.re, c.im) * amp[di]
+    partial = np.zeros(P.nslot, complex)
+    base = 0
+    seen = []
+    for order in segs:
+        steps, final, pj = D.window_program(order, jsets, window)
+        win = np.zeros(window, complex)
+        for (di, _, _), ops in zip(order, steps):
+            seen.append(di)
+            coef = {perm_index[q]: c for q, c in P.jcoef[di].items()}
+            for j, slot, flush in ops:
+                if flush is not None:
+                    partial[base + flush[1]] = win[flush[0]]
+                    win[flush[0]] = 0
+                c = coef[j]
+                win[slot] += complex(c.re, c.im) * amp[di]
+        for slot, pidx, _ in final:
+            partial[base + pidx] = win[slot]
+        base += len(pj)
+    assert sorted(seen) == list(range(len(P.diagrams)))
+    assert base == P.nslot
+    red = np.zeros(P.nc, complex)
+    for s, j in enumerate(P.partial_jamp):
+        red[j] += partial[s]
+    assert np.allclose(red, direct, atol=1e-12 * np.abs(direct).max())

@@ -424,11 +424,26 @@ __device__ __forceinline__ void lds_add(R* p, R v)
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 // jamp update in LDS: atomic add for double (ds_add_f64); plain read-add-write for float
-// (the FP32 LDS atomic add is much slower than the FP64 one on gfx950)
+// (the FP32 LDS atomic add is much slower than the FP64 one on gfx950).  A slot that
+// receives atomic adds is also read and cleared with atomic accesses: plain loads and
+// stores mixed with the no-return atomic adds on the same address were observed to be
+// reordered in the compiled code, while accesses that are all atomic keep their order.
 template <class R>
 __device__ __forceinline__ void jamp_add(R* p, R v)
 {
     if constexpr (sizeof(R) == 8) lds_add<R>(p, v);
     else *p += v;
+}
+template <class R>
+__device__ __forceinline__ R jamp_get(R* p)
+{
+    if constexpr (sizeof(R) == 8) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    else return *p;
+}
+template <class R>
+__device__ __forceinline__ void jamp_zero(R* p)
+{
+    if constexpr (sizeof(R) == 8) __hip_atomic_store(p, (R)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    else *p = (R)0;
 }
 }  // namespace me

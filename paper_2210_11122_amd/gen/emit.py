@@ -429,15 +429,24 @@ class Process:
             L.append(f"    // jamps accumulate in LDS, one private slot per lane ({jamp_mode})")
             L.append(f"    __shared__ {acc} Jl[2 * NW * 64];")
             L.append("#pragma unroll")
-            L.append(f"    for (int s = 0; s < 2 * NW; ++s) Jl[s * 64 + lane] = ({acc})0;")
+            if jamp_mode == "auto":
+                L.append("    for (int s = 0; s < 2 * NW; ++s) jamp_zero<R>(&Jl[s * 64 + lane]);")
+            else:
+                L.append(f"    for (int s = 0; s < 2 * NW; ++s) Jl[s * 64 + lane] = ({acc})0;")
             if jamp_mode == "rmw":
                 L.append("#define JADD(s, ri, v) (Jl[(2 * (s) + (ri)) * 64 + lane] += (v))")
+                L.append("#define JGET(s, ri) ((R)Jl[(2 * (s) + (ri)) * 64 + lane])")
+                L.append(f"#define JZERO(s, ri) (Jl[(2 * (s) + (ri)) * 64 + lane] = ({acc})0)")
             elif jamp_mode == "auto":
                 L.append("#define JADD(s, ri, v) jamp_add<R>(&Jl[(2 * (s) + (ri)) * 64 + lane], (v))")
+                L.append("#define JGET(s, ri) jamp_get<R>(&Jl[(2 * (s) + (ri)) * 64 + lane])")
+                L.append("#define JZERO(s, ri) jamp_zero<R>(&Jl[(2 * (s) + (ri)) * 64 + lane])")
             else:
                 L.append(f"#define JADD(s, ri, v) lds_add<{acc}>(&Jl[(2 * (s) + (ri)) * 64 + lane], ({acc})(v))")
-            L.append("#define JGET(s, ri) ((R)Jl[(2 * (s) + (ri)) * 64 + lane])")
-            L.append(f"#define JZERO(s, ri) (Jl[(2 * (s) + (ri)) * 64 + lane] = ({acc})0)")
+                L.append(f"#define JGET(s, ri) ((R)__hip_atomic_load(&Jl[(2 * (s) + (ri)) * 64 + lane], "
+                         "__ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT))")
+                L.append(f"#define JZERO(s, ri) __hip_atomic_store(&Jl[(2 * (s) + (ri)) * 64 + lane], ({acc})0, "
+                         "__ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT)")
         else:
             L.append("    R Jr[2 * NW];")
             L.append("#pragma unroll")

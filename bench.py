@@ -56,6 +56,30 @@ def timed_steps(proc, x, steps, warmup, torch):
     return out, (t1 - t0) * 1e3 / steps, lat, ms_amp, ms_cs, n_amp, n_cs
 
 
+def kernel_source_hash(process):
+    """hash of the sources that define the amplitude kernel of `process`"""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2210_11122_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ["helas.hpp", os.path.join("generated", f"proc_{process}.hip")]:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(process):
+    """HBM bytes per amplitude-kernel launch from the committed rocprofv3 counter summary, or
+    None when the kernel changed since the counters were taken"""
+    path = os.path.join(ROOT, "profiles", f"amp_kernel_{process}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_hash") != kernel_source_hash(process):
+        return None
+    return t
+
+
 def quantile(v, q):
     import numpy as np
     return float(np.quantile(np.asarray(v), q)) if len(v) else None
@@ -95,6 +119,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="also run one plain device copy of this size (for PMC byte calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the events are independent and the "
@@ -117,6 +143,12 @@ def main():
     x = p64.rambo(W.SEED, rs, n_evt)
     torch.cuda.synchronize()
 
+    if args.copy_calibration_mb:
+        a = torch.ones(args.copy_calibration_mb << 17, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     out64, ms64, lat64, ms_amp, ms_cs, n_amp, n_cs = timed_steps(p64, x, args.steps, args.warmup, torch)
     mes64 = n_evt / (ms64 / 1e3)
     lanes = n_evt * info["n_good_hel"]
@@ -151,7 +183,7 @@ def main():
             "peak": FP64_VALU_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tflops / FP64_VALU_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": None,  # filled below from the committed counter profile
             "flops_per_launch": flops_amp_step / max(amp_launches_per_step, 1),
             "avg_launch_ms": ms_amp / max(n_amp, 1),
             "launches_per_step": amp_launches_per_step,
@@ -163,6 +195,12 @@ def main():
             "ms_per_step": ms_cs / args.steps,
         },
     }
+
+    tr = measured_traffic(name)
+    if tr is not None:
+        result["roofline"]["traffic"] = tr["hbm_bytes_per_launch"]
+        result["roofline"]["traffic_source"] = tr["source"]
+        result["roofline"]["traffic_events_per_launch"] = tr["events_per_launch"]
 
     if not args.no_mixed:
         pm = Process(name, m_top=W.M_TOP, alpha_em=W.ALPHA_EM, alpha_s=W.ALPHA_S, precision="mixed_fp16")

@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-enum { ME_FP64 = 0, ME_MIXED_FP16 = 1 };
+enum { ME_FP64 = 0, ME_MIXED_FP16 = 1, ME_MIXED_BF16 = 2 };
 enum { ME_OK = 0, ME_EINVAL = -1, ME_ENOPROC = -2, ME_ENOMEM = -3, ME_EHIP = -4 };
 
 typedef struct me_handle me_handle; /* opaque, owned by the library */
@@ -42,9 +42,12 @@ typedef struct me_handle me_handle; /* opaque, owned by the library */
  * masses:    {m_t} or {m_t, w_t}; the top width must be 0 (no width in propagators).
  *            Ignored by ee_mumu and gg_gg.  NULL: m_t = 173.
  * couplings: {alpha_em, alpha_s}; NULL: {1/132.507, 0.118}.  Fixed couplings.
- * precision: ME_FP64 (all FP64) or ME_MIXED_FP16 (FP32 wavefunctions and amplitudes,
+ * precision: ME_FP64 (all FP64), ME_MIXED_FP16 (FP32 wavefunctions and amplitudes,
  *            FP16 matrix-core colour sum with FP32 accumulation, FP64 momenta,
- *            propagator denominators and helicity sum).
+ *            propagator denominators and helicity sum) or ME_MIXED_BF16 (as ME_MIXED_FP16
+ *            with BF16 matrix-core operands).  In both mixed forms each jamp column is
+ *            scaled by a power of two and split exactly into two 16-bit terms.  (The
+ *            paper's reduced-precision variant is all-single; Sec. 2, Tables 1 and 2.)
  * Copies the arrays, uploads the colour matrix and helicity table, and runs the
  * helicity-filter pre-pass: 1024 RAMBO events from the fixed seed 0x5EED, every helicity
  * evaluated, helicity h kept iff max_e |M_h(e)|^2 / |M(e)|^2 > 1e-20.  The mask does not
@@ -72,6 +75,25 @@ int me_sigma(me_handle *h, const double *momenta, int64_t n_evt, double *out_me2
 int me_sigma_hel(me_handle *h, const double *momenta, int64_t n_evt, double *out_me2, double *out_hel,
                  void *stream);
 
+/* As me_sigma, and also one helicity configuration and one colour flow per event, drawn
+ * from the event's own weights, as an unweighted event file records them (the two per-event
+ * choices the paper names as still missing from its event files, Sec. 4).
+ * rnd_hel, rnd_col: DEVICE double[n_evt], caller's uniforms in [0, 1).
+ * out_hel[e]: helicity-combination index (the numbering of me_helicity_ratios) drawn among
+ *             the good helicities with probability |M_h|^2 / sum_h |M_h|^2 (colour-summed);
+ * out_col[e]: colour-flow index k (the order of me_colour_flows) drawn with probability
+ *             w_k / sum_k w_k, w_k = sum_h |J_k,h|^2 the leading-colour weight of flow k.
+ * A draw takes the smallest index j with r * sum_i w_i < sum_{i<=j} w_i (FP64, index order).
+ * DEVICE int32 outputs of n_evt entries.  ME_EINVAL for NULL or host pointers. */
+int me_sigma_select(me_handle *h, const double *momenta, int64_t n_evt, const double *rnd_hel,
+                    const double *rnd_col, double *out_me2, int *out_hel, int *out_col, void *stream);
+
+/* colour flows: out[k * n_order + j] = the j-th gluon (0 = first gluon of the process) in
+ * the ordering of flow k, n_order = gluons on the quark line (gg_gg: the three gluons after
+ * gluon 3, which closes the trace; ee_mumu: 0).  out must hold n_colors * n_order ints.
+ * Returns n_colors. */
+int me_colour_flows(const me_handle *h, int *out);
+
 typedef struct {
     int n_par, n_diagrams, n_amplitudes, n_colors, n_hel, n_good_hel, precision;
     double avg_factor, sym_factor;
@@ -82,6 +104,8 @@ typedef struct {
     int64_t bytes_resident;    /* device bytes held by the handle (tables) */
     int64_t bytes_per_event_scratch; /* jamp scratch per event (per stream in use) */
     int64_t chunk_events;      /* events per amplitude/colour-sum launch pair */
+    int n_order;               /* entries per colour flow in me_colour_flows */
+    int helicity_groups;       /* colour-sum launches split the good helicities into this many groups */
 } me_info_t;
 
 int me_info(const me_handle *h, me_info_t *out);

@@ -210,3 +210,41 @@ def rambo(seed, sqrt_s, final_masses, n_evt, evt0=0):
     if rc != 0:
         raise ValueError("bad RAMBO arguments")
     return out
+
+
+# ----------------------------------------------------------------------------------------
+# Per-event helicity and colour-flow choice (the two per-event records of an unweighted
+# event that the paper, Sec. 4, lists as still missing): plain definitions.
+
+def helicity_weights(process, p, params=None):
+    """colour-summed |M_h|^2 of every helicity combination h (numbering as in ``me``)"""
+    return me(process, p, params=params, per_helicity=True)[1]
+
+
+def colour_weights(process, p, params=None):
+    """leading-colour weight of every colour flow sigma (order of ``orderings``):
+    w_sigma = sum over all helicities of |A_sigma|^2, the diagonal terms of the colour sum"""
+    nh = 1 << n_par(process)
+    w = None
+    for h in range(nh):
+        a = partials(process, p, h, params=params)
+        w = np.abs(a) ** 2 if w is None else w + np.abs(a) ** 2
+    return w
+
+
+def draw(weights, r):
+    """index j drawn from the weights with the uniform r in [0, 1): the smallest j with
+    r * W < w_0 + ... + w_j (W the total, all sums left to right in FP64); if rounding
+    leaves no such j, the last j of positive weight"""
+    total = 0.0
+    for x in weights:
+        total += float(x)
+    target = r * total
+    cum, last = 0.0, 0
+    for j, x in enumerate(weights):
+        cum += float(x)
+        if x > 0.0:
+            last = j
+        if target < cum:
+            return j
+    return last

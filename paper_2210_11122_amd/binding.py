@@ -10,8 +10,8 @@ import os
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libme.so")
 
-ME_FP64, ME_MIXED_FP16 = 0, 1
-PRECISIONS = {"fp64": ME_FP64, "mixed_fp16": ME_MIXED_FP16}
+ME_FP64, ME_MIXED_FP16, ME_MIXED_BF16 = 0, 1, 2
+PRECISIONS = {"fp64": ME_FP64, "mixed_fp16": ME_MIXED_FP16, "mixed_bf16": ME_MIXED_BF16}
 ME_OK = 0
 PROCESSES = ["ee_mumu", "gg_tt", "gg_ttg", "gg_ttgg", "gg_ttggg", "gg_gg"]
 
@@ -27,14 +27,15 @@ class MeInfo(ctypes.Structure):
                 ("flops_amp_lane", ctypes.c_double), ("flops_amp_exec_lane", ctypes.c_double),
                 ("n_partial_slots", ctypes.c_int), ("flops_colour_lane", ctypes.c_double),
                 ("bytes_resident", ctypes.c_int64), ("bytes_per_event_scratch", ctypes.c_int64),
-                ("chunk_events", ctypes.c_int64)]
+                ("chunk_events", ctypes.c_int64), ("n_order", ctypes.c_int), ("helicity_groups", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 EXPORTS = ["me_create", "me_destroy", "me_info", "me_last_error", "rambo_momenta", "me_sigma",
-           "me_sigma_hel", "me_good_helicities", "me_helicity_ratios", "me_profile"]
+           "me_sigma_hel", "me_sigma_select", "me_colour_flows", "me_good_helicities", "me_helicity_ratios",
+           "me_profile"]
 
 _lib = None
 
@@ -56,6 +57,8 @@ def load():
     L.rambo_momenta.argtypes = [vp, ctypes.c_uint64, ctypes.c_double, ctypes.c_int64, ctypes.c_int64, vp, vp]
     L.me_sigma.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
     L.me_sigma_hel.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp]
+    L.me_sigma_select.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp, vp, vp, vp]
+    L.me_colour_flows.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     L.me_good_helicities.argtypes = [vp, ctypes.POINTER(ctypes.c_byte)]
     L.me_helicity_ratios.argtypes = [vp, D]
     L.me_profile.argtypes = [vp, ctypes.c_int, D, D, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
@@ -136,6 +139,34 @@ class Process:
                                _stream_ptr(stream)), "me_sigma")
         return out
 
+    def select(self, momenta, r_hel, r_col, stream=None):
+        """(|M|^2, helicity-combination index, colour-flow index) per event, the two choices
+        drawn with the caller's uniforms r_hel, r_col (device float64 [n_evt])"""
+        import torch
+        assert momenta.is_cuda and momenta.dtype == torch.float64 and momenta.is_contiguous()
+        n = momenta.shape[0]
+        assert momenta.shape[1:] == (self.n_par, 4)
+        for r in (r_hel, r_col):
+            assert r.is_cuda and r.dtype == torch.float64 and r.is_contiguous() and r.shape == (n,)
+        out = torch.empty(n, dtype=torch.float64, device=momenta.device)
+        hel = torch.empty(n, dtype=torch.int32, device=momenta.device)
+        col = torch.empty(n, dtype=torch.int32, device=momenta.device)
+        _check(load().me_sigma_select(self._h, ctypes.c_void_p(momenta.data_ptr()), n,
+                                      ctypes.c_void_p(r_hel.data_ptr()), ctypes.c_void_p(r_col.data_ptr()),
+                                      ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(hel.data_ptr()),
+                                      ctypes.c_void_p(col.data_ptr()), _stream_ptr(stream)), "me_sigma_select")
+        return out, hel, col
+
+    def colour_flows(self):
+        """gluon ordering of every colour flow (list of tuples, flow order of the jamps)"""
+        nc = self.info["n_colors"]
+        buf = (ctypes.c_int * (nc * 8))()
+        n = load().me_colour_flows(self._h, buf)
+        if n < 0:
+            raise MeError(f"me_colour_flows failed: {last_error()}")
+        k = self.info["n_order"]
+        return [tuple(buf[f * k:(f + 1) * k]) for f in range(n)]
+
     def profile(self, enable):
         """switch launch timing on/off; returns what was recorded since the last call:
         (ms amplitude kernel, ms colour sum, launches of each)"""
@@ -150,6 +181,10 @@ class Process:
         buf = (ctypes.c_byte * (n * self.n_par))()
         load().me_good_helicities(self._h, buf)
         return [tuple(buf[k * self.n_par:(k + 1) * self.n_par]) for k in range(n)]
+
+    def good_helicities_index(self):
+        """helicity-combination index of every good helicity (particle i's bit at 2^(n_par-1-i))"""
+        return [sum(((l + 1) // 2) << (self.n_par - 1 - i) for i, l in enumerate(c)) for c in self.good_helicities()]
 
     def helicity_ratios(self):
         n = self.info["n_hel"]

@@ -14,7 +14,7 @@ LIB = os.path.join(PKG, "libme.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-# packed FP32 instructions are disabled on purpose ("Build flags")
+# packed FP32 instructions (v_pk_{add,mul,fma}_f32) are switched off for all device code
 FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]

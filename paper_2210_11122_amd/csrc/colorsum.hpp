@@ -8,15 +8,32 @@
 // event columns per wavefront, followed by the column dot product and the sum over the
 // filtered helicities in FP64.
 //
-// FP64 form: v_mfma_f64_16x16x4f64 (A = Chat tile 16x4, B = J tile 4x16, D 16x16 in FP64).
-// Mixed form: the FP32 jamps of one (event, helicity) are scaled by a power of two so that
-// the largest |J| lies in [1/2, 1), split exactly into two FP16 terms hi + lo * 2^-11, and
-// contracted with v_mfma_f32_16x16x16f16 (FP32 accumulation); the dot product is formed in
-// FP32 from the scaled FP32 jamps, unscaled exactly, and summed over helicities in FP64.
+// Symmetry: Chat is symmetric, so with the colour index cut into blocks of 16 the
+// contraction equals J^T A J for the block upper-triangular A with A = Chat on diagonal
+// blocks, 2 Chat above them and 0 below; only the tiles of A that touch the upper triangle
+// are multiplied (36 of 64 blocks for 120 flows).  The host prepares A in that form.
+//
+// Helicity groups: blockIdx.y selects a group of consecutive filtered helicities.  With one
+// group the kernel writes the averaged result; with several, each group writes its partial
+// sum to part[group][event] and hel_reduce adds the groups in a fixed order, so every
+// event's result is independent of the batch it came in.
+//
+// FP64 form: v_mfma_f64_16x16x4f64 (A tile 16x4, B tile 4x16, D 16x16, all FP64).
+// Mixed forms: the FP32 real (imaginary) rows of one (event, helicity) column are scaled by
+// a power of two so that their largest |J| lies in [1/2, 1), split exactly into two 16-bit
+// terms hi + lo * 2^-p (p = 11 for FP16, 8 for BF16), and contracted with
+// v_mfma_f32_16x16x32_{f16,bf16} (FP32 accumulation); the dot product is formed in FP32 from
+// the scaled FP32 jamps, unscaled exactly, and summed over helicities in FP64.  Colour
+// numerators that a 16-bit type cannot hold exactly (BF16 keeps 8 significant bits) are
+// split the same way on the host into A_hi + A_lo, both exact; tiles whose A_lo vanishes
+// are skipped by a per-tile mask.
 //
 // MFMA operand layouts (lane l, i = l % 16, g = l / 16):
-//   f64 16x16x4:  A[i][g], B[g][i], D[g + 4r][i] (r = 0..3)
-//   f16 16x16x16: A[i][4g + t], B[4g + t][i] (t = 0..3), D[4g + r][i]
+//   f64 16x16x4:   A[i][g], B[g][i], D[g + 4r][i] (r = 0..3)
+//   16x16x32:      A[i][8g + t], B[8g + t][i] (t = 0..7), D[4g + r][i]
+// In the 16x16x32 form the k slot (kb, 8g + t) carries colour 16 (2 kb + t / 4) + 4 g + t % 4,
+// so that the B elements a lane holds are exactly the D rows it receives (the dot product
+// then needs no data exchange between lanes).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -25,7 +42,8 @@ namespace me {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
-typedef _Float16 v4h __attribute__((ext_vector_type(4)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ double sum_lane_groups(double x)
 {
@@ -40,16 +58,53 @@ __device__ __forceinline__ float max_lane_groups(float x)
     return x;
 }
 
-// A operands of Chat for the f64 MFMA, pre-arranged per lane: aop[(mt * KT + kt) * 64 + l]
-// = Chat[16 mt + l % 16][4 kt + l / 16] (zero outside NC).
+// tile counts of the block upper-triangular colour matrix
+__host__ __device__ constexpr int cs64_tiles(int nc)
+{
+    int n = 0;
+    for (int mt = 0; mt < (nc + 15) / 16; ++mt)
+        for (int kt = 4 * mt; kt < (nc + 3) / 4; ++kt) ++n;
+    return n;
+}
+__host__ __device__ constexpr int cs16_tiles(int nc)
+{
+    int n = 0;
+    for (int mt = 0; mt < (nc + 15) / 16; ++mt)
+        for (int kb = mt / 2; kb < ((nc + 15) / 16 + 1) / 2; ++kb) ++n;
+    return n;
+}
+
+// the colour-matrix operands are re-read from the cache for every helicity: hiding the table
+// pointer from loop-invariant code motion keeps the compiler from hoisting all of them into
+// registers (which would leave one wave per SIMD for the large matrix)
+template <class P>
+__device__ __forceinline__ const P* opaque(const P* p)
+{
+    __asm__ volatile("" : "+s"(p));
+    return p;
+}
+
+// store or accumulate the helicity-group result of one event
+__device__ __forceinline__ void cs_store(double me, int64_t e, int64_t n_evt, double scale_avg, double* out,
+                                         double* part)
+{
+    if (gridDim.y == 1)
+        out[e] = me * scale_avg;
+    else
+        part[(int64_t)blockIdx.y * n_evt + e] = me;
+}
+
+// A operands, per lane, in the kernel's tile order (mt ascending, then kt >= 4 mt):
+// aop[q * 64 + l] = A[16 mt + l % 16][4 kt + l / 16].
 template <int NC>
 __global__ __launch_bounds__(256) void colour_sum_f64(const double* __restrict__ J, int64_t ld, int n_good,
-                                                      int64_t n_evt, const double* __restrict__ aop,
-                                                      double scale_hel, double scale_avg,
-                                                      double* __restrict__ out, double* __restrict__ out_hel)
+                                                      int hel_per_group, int64_t n_evt,
+                                                      const double* __restrict__ aop, double scale_hel,
+                                                      double scale_avg, double* __restrict__ out,
+                                                      double* __restrict__ out_hel, double* __restrict__ part)
 {
-    constexpr int MT = (NC + 15) / 16, KT = (NC + 3) / 4;
-    constexpr bool AREG = MT * KT <= 24;
+    constexpr int MT = (NC + 15) / 16, KT = (NC + 3) / 4, NT = cs64_tiles(NC);
+    constexpr bool AREG = NT <= 24;
     const int lane = threadIdx.x & 63;
     const int64_t e0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
     if (e0 >= n_evt) return;
@@ -57,55 +112,86 @@ __global__ __launch_bounds__(256) void colour_sum_f64(const double* __restrict__
     const int64_t e = e0 + i;
     const bool valid = e < n_evt;
     const int64_t ec = valid ? e : n_evt - 1;
-    double A[AREG ? MT * KT : 1];
+    const int h0 = blockIdx.y * hel_per_group, h1 = min(n_good, h0 + hel_per_group);
+    double A[AREG ? NT : 1];
     if (AREG) {
 #pragma unroll
-        for (int q = 0; q < MT * KT; ++q) A[q] = aop[q * 64 + lane];
+        for (int q = 0; q < NT; ++q) A[q] = aop[q * 64 + lane];
     }
     double me = 0.0;
-    for (int h = 0; h < n_good; ++h) {
+    for (int h = h0; h < h1; ++h) {
         const double* Jh = J + (int64_t)h * (2 * NC) * ld;
-        double part = 0.0;
-#pragma unroll
+        double part_h = 0.0;
+#pragma unroll 1
         for (int ri = 0; ri < 2; ++ri) {
-            v4d d[MT];
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) d[mt] = (v4d){0.0, 0.0, 0.0, 0.0};
+            // this lane's B elements: colours c = 4 kt + g, which are also its D rows
+            double b[KT];
 #pragma unroll
             for (int kt = 0; kt < KT; ++kt) {
                 const int c = 4 * kt + g;
-                const double b = (c < NC) ? Jh[(int64_t)(2 * c + ri) * ld + ec] : 0.0;
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt) {
-                    const double a = AREG ? A[mt * KT + kt] : aop[(mt * KT + kt) * 64 + lane];
-                    d[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, d[mt], 0, 0, 0);
-                }
+                b[kt] = (c < NC) ? Jh[(int64_t)(2 * c + ri) * ld + ec] : 0.0;
             }
+            int q = 0;
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
+            for (int mt = 0; mt < MT; ++mt) {
+                const double* ap = opaque(aop);
+                v4d d = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int c = 16 * mt + g + 4 * r;
-                    if (c < NC) part += Jh[(int64_t)(2 * c + ri) * ld + ec] * d[mt][r];
+                for (int kt = 4 * mt; kt < KT; ++kt, ++q) {
+                    const double a = AREG ? A[q] : ap[q * 64 + lane];
+                    d = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[kt], d, 0, 0, 0);
                 }
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (4 * mt + r < KT) part_h += b[4 * mt + r] * d[r];
+            }
         }
-        part = sum_lane_groups(part);
-        if (out_hel && g == 0 && valid) out_hel[e * n_good + h] = part * scale_hel;
-        me += part;
+        part_h = sum_lane_groups(part_h);
+        if (out_hel && g == 0 && valid) out_hel[e * n_good + h] = part_h * scale_hel;
+        me += part_h;
     }
-    if (g == 0 && valid) out[e] = me * scale_avg;
+    if (g == 0 && valid) cs_store(me, e, n_evt, scale_avg, out, part);
 }
 
-// A operands of Chat for the f16 MFMA: aop[((mt * KB + kb) * 64 + l) * 4 + t]
-// = Chat[16 mt + l % 16][16 kb + 4 (l / 16) + t].
-template <int NC>
-__global__ __launch_bounds__(256) void colour_sum_f16(const float* __restrict__ J, int64_t ld, int n_good,
-                                                      int64_t n_evt, const _Float16* __restrict__ aop,
-                                                      double scale_hel, double scale_avg,
-                                                      double* __restrict__ out, double* __restrict__ out_hel)
+// 16-bit element types of the mixed colour sum
+struct Fp16Terms {
+    typedef _Float16 elem;
+    typedef v8h vec;
+    static constexpr float LO = 2048.0f;  // hi keeps 11 significant bits
+    static __device__ __forceinline__ elem round(float v) { return (_Float16)v; }
+    static __device__ __forceinline__ float value(elem x) { return (float)x; }
+    static __device__ __forceinline__ v4f mfma(vec a, vec b, v4f c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+};
+struct Bf16Terms {
+    typedef __bf16 elem;
+    typedef v8bf vec;
+    static constexpr float LO = 256.0f;  // hi keeps 8 significant bits
+    static __device__ __forceinline__ elem round(float v) { return (__bf16)v; }
+    static __device__ __forceinline__ float value(elem x) { return (float)x; }
+    static __device__ __forceinline__ v4f mfma(vec a, vec b, v4f c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+
+// A operands, per lane, in the kernel's tile order (mt ascending, then kb >= mt / 2):
+// aop[(q * 64 + l) * 8 + t] = A[16 mt + l % 16][colour of k slot (kb, 8 (l / 16) + t)].
+// aop_lo (A_lo, same layout) is read for the tiles whose bit is set in lo_mask.
+template <int NC, class T>
+__global__ __launch_bounds__(256) void colour_sum_h16(const float* __restrict__ J, int64_t ld, int n_good,
+                                                      int hel_per_group, int64_t n_evt,
+                                                      const typename T::elem* __restrict__ aop,
+                                                      const typename T::elem* __restrict__ aop_lo, uint64_t lo_mask,
+                                                      double scale_hel, double scale_avg, double* __restrict__ out,
+                                                      double* __restrict__ out_hel, double* __restrict__ part)
 {
-    constexpr int MT = (NC + 15) / 16, KB = MT;
-    constexpr bool AREG = MT * KB <= 16;
+    typedef typename T::vec vec;
+    typedef typename T::elem elem;
+    constexpr int MT = (NC + 15) / 16, KB = (MT + 1) / 2, NT = cs16_tiles(NC);
+    constexpr bool AREG = NT <= 8;
     const int lane = threadIdx.x & 63;
     const int64_t e0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
     if (e0 >= n_evt) return;
@@ -113,65 +199,85 @@ __global__ __launch_bounds__(256) void colour_sum_f16(const float* __restrict__ 
     const int64_t e = e0 + i;
     const bool valid = e < n_evt;
     const int64_t ec = valid ? e : n_evt - 1;
-    v4h A[AREG ? MT * KB : 1];
+    const int h0 = blockIdx.y * hel_per_group, h1 = min(n_good, h0 + hel_per_group);
+    vec A[AREG ? NT : 1];
     if (AREG) {
 #pragma unroll
-        for (int q = 0; q < MT * KB; ++q) A[q] = *reinterpret_cast<const v4h*>(aop + (q * 64 + lane) * 4);
+        for (int q = 0; q < NT; ++q) A[q] = *reinterpret_cast<const vec*>(aop + (q * 64 + lane) * 8);
     }
     double me = 0.0;
-    for (int h = 0; h < n_good; ++h) {
+    for (int h = h0; h < h1; ++h) {
         const float* Jh = J + (int64_t)h * (2 * NC) * ld;
-        // this lane's rows of column i: c = 16 kb + 4 g + t
-        float x[2][KB][4];
-        float mx = 0.0f;
-#pragma unroll
-        for (int ri = 0; ri < 2; ++ri)
+        double part_h = 0.0;
+#pragma unroll 1
+        for (int ri = 0; ri < 2; ++ri) {
+            // x[kb][t]: colour 16 (2 kb + t / 4) + 4 g + t % 4 of column i
+            float x[KB][8];
+            float mx = 0.0f;
 #pragma unroll
             for (int kb = 0; kb < KB; ++kb)
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int c = 16 * kb + 4 * g + t;
+                for (int t = 0; t < 8; ++t) {
+                    const int c = 16 * (2 * kb + t / 4) + 4 * g + t % 4;
                     const float v = (c < NC) ? Jh[(int64_t)(2 * c + ri) * ld + ec] : 0.0f;
-                    x[ri][kb][t] = v;
+                    x[kb][t] = v;
                     mx = fmaxf(mx, fabsf(v));
                 }
-        mx = max_lane_groups(mx);
-        // power-of-two scale: largest |J| of the column into [1/2, 1)
-        int ex = 0;
-        if (mx > 0.0f) frexpf(mx, &ex);
-        const float s = ldexpf(1.0f, -ex);
-        float part = 0.0f;
-#pragma unroll
-        for (int ri = 0; ri < 2; ++ri) {
-            v4h bh[KB], bl[KB];
+            mx = max_lane_groups(mx);
+            // power-of-two scale: largest |J| of the column into [1/2, 1)
+            int ex = 0;
+            if (mx > 0.0f) frexpf(mx, &ex);
+            const float s = ldexpf(1.0f, -ex);
+            vec bh[KB], bl[KB];
 #pragma unroll
             for (int kb = 0; kb < KB; ++kb)
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const float v = x[ri][kb][t] * s;
-                    const _Float16 hi = (_Float16)v;
+                for (int t = 0; t < 8; ++t) {
+                    const float v = x[kb][t] * s;
+                    const elem hi = T::round(v);
                     bh[kb][t] = hi;
-                    bl[kb][t] = (_Float16)((v - (float)hi) * 2048.0f);
-                    x[ri][kb][t] = v;
+                    bl[kb][t] = T::round((v - T::value(hi)) * T::LO);
+                    x[kb][t] = v;
                 }
+            float acc = 0.0f;
+            int q = 0;
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
+                const elem* ap = opaque(aop);
+                const elem* ap_lo = opaque(aop_lo);
                 v4f dh = {0.f, 0.f, 0.f, 0.f}, dl = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int kb = 0; kb < KB; ++kb) {
-                    const v4h a = AREG ? A[mt * KB + kb] : *reinterpret_cast<const v4h*>(aop + ((mt * KB + kb) * 64 + lane) * 4);
-                    dh = __builtin_amdgcn_mfma_f32_16x16x16f16(a, bh[kb], dh, 0, 0, 0);
-                    dl = __builtin_amdgcn_mfma_f32_16x16x16f16(a, bl[kb], dl, 0, 0, 0);
+                for (int kb = mt / 2; kb < KB; ++kb, ++q) {
+                    const vec a = AREG ? A[q] : *reinterpret_cast<const vec*>(ap + (q * 64 + lane) * 8);
+                    dh = T::mfma(a, bh[kb], dh);
+                    dl = T::mfma(a, bl[kb], dl);
+                    if ((lo_mask >> q) & 1) {
+                        const vec alo = *reinterpret_cast<const vec*>(ap_lo + (q * 64 + lane) * 8);
+                        dh = T::mfma(alo, bh[kb], dh);
+                    }
                 }
+                // D rows 16 mt + 4 g + r are this lane's x[mt / 2][4 (mt % 2) + r]
 #pragma unroll
-                for (int r = 0; r < 4; ++r) part += x[ri][mt][r] * (dh[r] + dl[r] * (1.0f / 2048.0f));
+                for (int r = 0; r < 4; ++r) acc += x[mt / 2][4 * (mt % 2) + r] * (dh[r] + dl[r] * (1.0f / T::LO));
             }
+            part_h += (double)acc / ((double)s * (double)s);
         }
-        double p = sum_lane_groups((double)part) / ((double)s * (double)s);
-        if (out_hel && g == 0 && valid) out_hel[e * n_good + h] = p * scale_hel;
-        me += p;
+        part_h = sum_lane_groups(part_h);
+        if (out_hel && g == 0 && valid) out_hel[e * n_good + h] = part_h * scale_hel;
+        me += part_h;
     }
-    if (g == 0 && valid) out[e] = me * scale_avg;
+    if (g == 0 && valid) cs_store(me, e, n_evt, scale_avg, out, part);
+}
+
+// out[e] = scale * sum over helicity groups of part[group][e], groups in order
+__global__ __launch_bounds__(256) void hel_reduce(const double* __restrict__ part, int groups, int64_t n_evt,
+                                                  double scale, double* __restrict__ out)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n_evt) return;
+    double s = 0.0;
+    for (int k = 0; k < groups; ++k) s += part[(int64_t)k * n_evt + e];
+    out[e] = s * scale;
 }
 
 }  // namespace me

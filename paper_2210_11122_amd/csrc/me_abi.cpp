@@ -19,6 +19,7 @@
 #include "colorsum.hpp"
 #include "process.hpp"
 #include "rambo.hpp"
+#include "select.hpp"
 
 namespace {
 
@@ -50,6 +51,7 @@ constexpr int64_t SCRATCH_EVENTS = 4096;          // room for 4096 events, at mo
 constexpr int PREPASS_EVENTS = 1024;
 constexpr uint64_t PREPASS_SEED = 0x5EED;
 constexpr double PREPASS_THRESHOLD = 1e-20;
+constexpr int64_t COLOUR_TARGET_WAVES = 8192;   // colour-sum waves per launch the helicity split aims for
 
 bool is_device_pointer(const void* p)
 {
@@ -71,10 +73,16 @@ struct me_handle {
     double mt = 173.0, alpha_em = 1.0 / 132.507, alpha_s = 0.118, g = 0.0;
     int n_good = 0;
     signed char* d_hel_good = nullptr;
+    int* d_hel_index = nullptr;  // helicity-combination index of each good helicity
     std::vector<signed char> h_hel_good;
     std::vector<double> hel_ratio;
     double* d_aop64 = nullptr;
     _Float16* d_aop16 = nullptr;
+    __bf16* d_aopb = nullptr;      // BF16 A_hi
+    __bf16* d_aopb_lo = nullptr;   // BF16 A_lo (exact remainder of numerators BF16 cannot hold)
+    uint64_t lo_mask_b16 = 0;      // tiles with a non-zero A_lo
+    int groups = 1, hel_per_group = 1;  // helicity split of the colour sum
+    size_t jamp_bytes_per_event = 0;
     size_t bytes_resident = 0;
     int64_t chunk = 0;
     size_t bytes_per_event = 0;
@@ -95,47 +103,84 @@ namespace {
 // ---------------------------------------------------------------------------------------
 // kernel dispatch over the compile-time colour-flow count
 
+struct ColourArgs {
+    int64_t ld;
+    int n_good, hel_per_group, groups;
+    int64_t n;
+    double scale_hel, scale_avg;
+    double *out, *out_hel, *part;
+};
+
 template <int NC>
-hipError_t launch_cs64(const double* J, int64_t ld, int n_good, int64_t n, const double* aop, double sh, double sa,
-                       double* out, double* out_hel, hipStream_t st)
+hipError_t launch_cs64(const double* J, const double* aop, const ColourArgs& a, hipStream_t st)
 {
-    hipLaunchKernelGGL(me::colour_sum_f64<NC>, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, st, J, ld, n_good, n,
-                       aop, sh, sa, out, out_hel);
+    hipLaunchKernelGGL(me::colour_sum_f64<NC>, dim3((unsigned)((a.n + 63) / 64), (unsigned)a.groups), dim3(256), 0,
+                       st, J, a.ld, a.n_good, a.hel_per_group, a.n, aop, a.scale_hel, a.scale_avg, a.out, a.out_hel,
+                       a.part);
     return hipGetLastError();
 }
-template <int NC>
-hipError_t launch_cs16(const float* J, int64_t ld, int n_good, int64_t n, const _Float16* aop, double sh, double sa,
-                       double* out, double* out_hel, hipStream_t st)
+template <int NC, class T>
+hipError_t launch_cs16(const float* J, const typename T::elem* aop, const typename T::elem* aop_lo, uint64_t lo_mask,
+                       const ColourArgs& a, hipStream_t st)
 {
-    hipLaunchKernelGGL(me::colour_sum_f16<NC>, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, st, J, ld, n_good, n,
-                       aop, sh, sa, out, out_hel);
+    hipLaunchKernelGGL((me::colour_sum_h16<NC, T>), dim3((unsigned)((a.n + 63) / 64), (unsigned)a.groups), dim3(256),
+                       0, st, J, a.ld, a.n_good, a.hel_per_group, a.n, aop, aop_lo, lo_mask, a.scale_hel, a.scale_avg,
+                       a.out, a.out_hel, a.part);
+    return hipGetLastError();
+}
+template <class T>
+hipError_t dispatch_cs16(int nc, const float* j, const typename T::elem* aop, const typename T::elem* aop_lo,
+                         uint64_t lo_mask, const ColourArgs& a, hipStream_t st)
+{
+    switch (nc) {
+    case 1: return launch_cs16<1, T>(j, aop, aop_lo, lo_mask, a, st);
+    case 2: return launch_cs16<2, T>(j, aop, aop_lo, lo_mask, a, st);
+    case 6: return launch_cs16<6, T>(j, aop, aop_lo, lo_mask, a, st);
+    case 24: return launch_cs16<24, T>(j, aop, aop_lo, lo_mask, a, st);
+    case 120: return launch_cs16<120, T>(j, aop, aop_lo, lo_mask, a, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+// colour sum of one chunk; with several helicity groups the partial sums go through `part`
+// (groups x n doubles) and a fixed-order reduction
+hipError_t colour_sum(const me_handle* h, int precision, const void* J, int64_t ld, int n_good, int hel_per_group,
+                      int groups, int64_t n, double* out, double* out_hel, double* part, hipStream_t st)
+{
+    const double sh = 1.0 / h->P->colour_den, sa = 1.0 / ((double)h->P->colour_den * h->P->avg);
+    const ColourArgs a{ld, n_good, hel_per_group, groups, n, sh, sa, out, out_hel, part};
+    hipError_t e = hipErrorInvalidValue;
+    if (precision == ME_FP64) {
+        const double* j = static_cast<const double*>(J);
+        switch (h->P->nc) {
+        case 1: e = launch_cs64<1>(j, h->d_aop64, a, st); break;
+        case 2: e = launch_cs64<2>(j, h->d_aop64, a, st); break;
+        case 6: e = launch_cs64<6>(j, h->d_aop64, a, st); break;
+        case 24: e = launch_cs64<24>(j, h->d_aop64, a, st); break;
+        case 120: e = launch_cs64<120>(j, h->d_aop64, a, st); break;
+        }
+    } else if (precision == ME_MIXED_FP16) {
+        e = dispatch_cs16<me::Fp16Terms>(h->P->nc, static_cast<const float*>(J), h->d_aop16, h->d_aop16, 0, a, st);
+    } else {
+        e = dispatch_cs16<me::Bf16Terms>(h->P->nc, static_cast<const float*>(J), h->d_aopb, h->d_aopb_lo,
+                                         h->lo_mask_b16, a, st);
+    }
+    if (e != hipSuccess || groups == 1) return e;
+    hipLaunchKernelGGL(me::hel_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part, groups, n, sa, out);
     return hipGetLastError();
 }
 
-hipError_t colour_sum(const me_handle* h, bool fp64, const void* J, int64_t ld, int n_good, int64_t n, double* out,
-                      double* out_hel, hipStream_t st)
+// helicity groups of the colour sum for launches of up to `chunk` events: enough
+// (event tile, group) waves to fill the device when a chunk alone does not
+void helicity_groups(const me::ProcessDesc* P, int n_good, int64_t chunk, int* groups, int* hel_per_group)
 {
-    const double sh = 1.0 / h->P->colour_den, sa = 1.0 / ((double)h->P->colour_den * h->P->avg);
-    if (fp64) {
-        const double* j = static_cast<const double*>(J);
-        switch (h->P->nc) {
-        case 1: return launch_cs64<1>(j, ld, n_good, n, h->d_aop64, sh, sa, out, out_hel, st);
-        case 2: return launch_cs64<2>(j, ld, n_good, n, h->d_aop64, sh, sa, out, out_hel, st);
-        case 6: return launch_cs64<6>(j, ld, n_good, n, h->d_aop64, sh, sa, out, out_hel, st);
-        case 24: return launch_cs64<24>(j, ld, n_good, n, h->d_aop64, sh, sa, out, out_hel, st);
-        case 120: return launch_cs64<120>(j, ld, n_good, n, h->d_aop64, sh, sa, out, out_hel, st);
-        }
-    } else {
-        const float* j = static_cast<const float*>(J);
-        switch (h->P->nc) {
-        case 1: return launch_cs16<1>(j, ld, n_good, n, h->d_aop16, sh, sa, out, out_hel, st);
-        case 2: return launch_cs16<2>(j, ld, n_good, n, h->d_aop16, sh, sa, out, out_hel, st);
-        case 6: return launch_cs16<6>(j, ld, n_good, n, h->d_aop16, sh, sa, out, out_hel, st);
-        case 24: return launch_cs16<24>(j, ld, n_good, n, h->d_aop16, sh, sa, out, out_hel, st);
-        case 120: return launch_cs16<120>(j, ld, n_good, n, h->d_aop16, sh, sa, out, out_hel, st);
-        }
+    int64_t G = 1;
+    if (P->nc > 6) {
+        const int64_t waves = (chunk + 15) / 16;
+        G = std::min<int64_t>(std::max<int64_t>((COLOUR_TARGET_WAVES + waves - 1) / waves, 1), n_good);
     }
-    return hipErrorInvalidValue;
+    *hel_per_group = (int)((n_good + G - 1) / G);
+    *groups = (n_good + *hel_per_group - 1) / *hel_per_group;
 }
 
 template <int NF>
@@ -189,10 +234,22 @@ struct TimedLaunch {
 };
 
 // amplitude kernel + colour sum for events [0, n) of `mom`, in chunks through `jamp`
-int run_chunks(me_handle* h, bool fp64, const signed char* hel, int n_good, int64_t chunk, const double* mom,
-               int64_t n, double* out, double* out_hel, void* jamp, hipStream_t st, bool timed = false)
+// per-event helicity and colour-flow draws (select.hpp); hel_me and w are chunk scratch
+struct Selection {
+    const double *r_hel, *r_col;
+    int *out_hel, *out_col;
+    double *hel_me, *w;
+};
+
+// scratch: jamps of `chunk` events (jamp_bytes_per_event each), then the helicity-group partial sums
+int run_chunks(me_handle* h, int precision, const signed char* hel, int n_good, int hel_per_group, int groups,
+               int64_t chunk, size_t jamp_bytes_per_event, const double* mom, int64_t n, double* out, double* out_hel,
+               void* scratch, hipStream_t st, bool timed = false, const Selection* sel = nullptr)
 {
     const me::ProcessDesc* P = h->P;
+    const bool fp64 = precision == ME_FP64;
+    void* jamp = scratch;
+    double* part = reinterpret_cast<double*>(static_cast<char*>(scratch) + (size_t)chunk * jamp_bytes_per_event);
     for (int64_t c0 = 0; c0 < n; c0 += chunk) {
         const int64_t nc = std::min(chunk, n - c0);
         const int64_t ld = (nc + 63) / 64 * 64;
@@ -203,9 +260,24 @@ int run_chunks(me_handle* h, bool fp64, const signed char* hel, int n_good, int6
         ta.done();
         if (e != hipSuccess) return fail(ME_EHIP, std::string("amplitude kernel: ") + hipGetErrorString(e));
         TimedLaunch tc(h, st, 1, timed);
-        e = colour_sum(h, fp64, jamp, ld, n_good, nc, out + c0, out_hel ? out_hel + c0 * n_good : nullptr, st);
+        double* oh = sel ? sel->hel_me : (out_hel ? out_hel + c0 * n_good : nullptr);
+        e = colour_sum(h, precision, jamp, ld, n_good, hel_per_group, groups, nc, out + c0, oh, part, st);
         tc.done();
         if (e != hipSuccess) return fail(ME_EHIP, std::string("colour-sum kernel: ") + hipGetErrorString(e));
+        if (sel) {
+            const dim3 grid((unsigned)((nc + 255) / 256), (unsigned)P->nc);
+            if (fp64)
+                hipLaunchKernelGGL(me::lc_weights<double>, grid, dim3(256), 0, st, static_cast<const double*>(jamp), ld,
+                                   P->nc, n_good, nc, sel->w);
+            else
+                hipLaunchKernelGGL(me::lc_weights<float>, grid, dim3(256), 0, st, static_cast<const float*>(jamp), ld,
+                                   P->nc, n_good, nc, sel->w);
+            hipLaunchKernelGGL(me::select_events, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, sel->hel_me,
+                               n_good, sel->w, P->nc, nc, h->d_hel_index, sel->r_hel + c0, sel->r_col + c0,
+                               sel->out_hel + c0, sel->out_col + c0);
+            e = hipGetLastError();
+            if (e != hipSuccess) return fail(ME_EHIP, std::string("selection kernels: ") + hipGetErrorString(e));
+        }
     }
     return ME_OK;
 }
@@ -224,39 +296,68 @@ void free_handle(me_handle* h)
         (void)hipEventDestroy(m.b);
     }
     if (h->d_hel_good) (void)hipFree(h->d_hel_good);
+    if (h->d_hel_index) (void)hipFree(h->d_hel_index);
     if (h->d_aop64) (void)hipFree(h->d_aop64);
     if (h->d_aop16) (void)hipFree(h->d_aop16);
+    if (h->d_aopb) (void)hipFree(h->d_aopb);
+    if (h->d_aopb_lo) (void)hipFree(h->d_aopb_lo);
     delete h;
 }
 
-// colour matrix as matrix-core A operands (see colorsum.hpp for the layouts)
+// colour matrix as matrix-core A operands, block upper-triangular (see colorsum.hpp for the
+// layouts and the tile order)
 int upload_colour(me_handle* h)
 {
     const me::ProcessDesc* P = h->P;
     const int NC = P->nc;
-    const int MT = (NC + 15) / 16, KT = (NC + 3) / 4, KB = MT;
-    auto C = [&](int r, int c) -> double { return (r < NC && c < NC) ? P->colour_num[r * NC + c] : 0.0; };
-    std::vector<double> a64((size_t)MT * KT * 64);
+    const int MT = (NC + 15) / 16, KT = (NC + 3) / 4, KB = (MT + 1) / 2;
+    // A[r][c] = w * Chat[r][c], w = 1 on diagonal 16-blocks, 2 above, 0 below
+    auto A = [&](int r, int c) -> double {
+        if (r >= NC || c >= NC || c / 16 < r / 16) return 0.0;
+        return (c / 16 == r / 16 ? 1.0 : 2.0) * P->colour_num[r * NC + c];
+    };
+    std::vector<double> a64;
     for (int mt = 0; mt < MT; ++mt)
-        for (int kt = 0; kt < KT; ++kt)
-            for (int l = 0; l < 64; ++l) a64[((size_t)mt * KT + kt) * 64 + l] = C(16 * mt + l % 16, 4 * kt + l / 16);
-    std::vector<_Float16> a16((size_t)MT * KB * 64 * 4);
+        for (int kt = 4 * mt; kt < KT; ++kt)
+            for (int l = 0; l < 64; ++l) a64.push_back(A(16 * mt + l % 16, 4 * kt + l / 16));
+    std::vector<_Float16> a16;
+    std::vector<__bf16> ab, ablo;
+    uint64_t lo_mask = 0;
+    int q = 0;
     for (int mt = 0; mt < MT; ++mt)
-        for (int kb = 0; kb < KB; ++kb)
+        for (int kb = mt / 2; kb < KB; ++kb, ++q) {
+            bool lo_used = false;
             for (int l = 0; l < 64; ++l)
-                for (int t = 0; t < 4; ++t) {
-                    const double v = C(16 * mt + l % 16, 16 * kb + 4 * (l / 16) + t);
+                for (int t = 0; t < 8; ++t) {
+                    const int c = 16 * (2 * kb + t / 4) + 4 * (l / 16) + t % 4;
+                    const double v = A(16 * mt + l % 16, c);
                     const _Float16 x = (_Float16)v;
                     if ((double)x != v) return fail(ME_EINVAL, "colour matrix numerator not exact in FP16");
-                    a16[(((size_t)mt * KB + kb) * 64 + l) * 4 + t] = x;
+                    a16.push_back(x);
+                    const __bf16 hi = (__bf16)(float)v;
+                    const double rest = v - (double)(float)hi;
+                    const __bf16 lo = (__bf16)(float)rest;
+                    if ((double)(float)lo != rest) return fail(ME_EINVAL, "colour matrix numerator not exact in two BF16 terms");
+                    ab.push_back(hi);
+                    ablo.push_back(lo);
+                    lo_used |= rest != 0.0;
                 }
-    if (hipMalloc(&h->d_aop64, a64.size() * sizeof(double)) != hipSuccess ||
-        hipMalloc(&h->d_aop16, a16.size() * sizeof(_Float16)) != hipSuccess)
+            if (lo_used) {
+                if (q >= 64) return fail(ME_EINVAL, "colour matrix too large for the BF16 tile mask");
+                lo_mask |= uint64_t(1) << q;
+            }
+        }
+    h->lo_mask_b16 = lo_mask;
+    const size_t b64 = a64.size() * sizeof(double), b16 = a16.size() * sizeof(_Float16), bb = ab.size() * sizeof(__bf16);
+    if (hipMalloc(&h->d_aop64, b64) != hipSuccess || hipMalloc(&h->d_aop16, b16) != hipSuccess ||
+        hipMalloc(&h->d_aopb, bb) != hipSuccess || hipMalloc(&h->d_aopb_lo, bb) != hipSuccess)
         return fail(ME_ENOMEM, "hipMalloc of the colour tables failed");
-    if (hipMemcpy(h->d_aop64, a64.data(), a64.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(h->d_aop16, a16.data(), a16.size() * sizeof(_Float16), hipMemcpyHostToDevice) != hipSuccess)
+    if (hipMemcpy(h->d_aop64, a64.data(), b64, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->d_aop16, a16.data(), b16, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->d_aopb, ab.data(), bb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->d_aopb_lo, ablo.data(), bb, hipMemcpyHostToDevice) != hipSuccess)
         return fail(ME_EHIP, "upload of the colour tables failed");
-    h->bytes_resident += a64.size() * sizeof(double) + a16.size() * sizeof(_Float16);
+    h->bytes_resident += b64 + b16 + 2 * bb;
     return ME_OK;
 }
 
@@ -272,9 +373,12 @@ int helicity_prepass(me_handle* h, hipStream_t st)
     const double sqrt_s = P->coupling ? 1500.0 : 500.0;
     signed char* d_all = nullptr;
     double *d_mom = nullptr, *d_out = nullptr, *d_hel = nullptr, *d_jamp = nullptr;
-    const size_t per_event = (size_t)nhel * 2 * (P->nc + P->nslot) * sizeof(double);
-    const int64_t pchunk = std::min<int64_t>(n, std::max<int64_t>(64, (int64_t)((size_t(512) << 20) / per_event) / 64 * 64));
-    const size_t jbytes = per_event * pchunk;
+    const size_t jamp_per_event = (size_t)nhel * 2 * (P->nc + P->nslot) * sizeof(double);
+    const int64_t pchunk =
+        std::min<int64_t>(n, std::max<int64_t>(64, (int64_t)((size_t(512) << 20) / jamp_per_event) / 64 * 64));
+    int groups = 1, hpg = 1;
+    helicity_groups(P, nhel, pchunk, &groups, &hpg);
+    const size_t jbytes = (jamp_per_event + groups * sizeof(double)) * pchunk;
     int rc = ME_OK;
     if (hipMalloc(&d_all, all.size()) != hipSuccess || hipMalloc(&d_mom, n * npar * 4 * sizeof(double)) != hipSuccess ||
         hipMalloc(&d_out, n * sizeof(double)) != hipSuccess ||
@@ -286,7 +390,8 @@ int helicity_prepass(me_handle* h, hipStream_t st)
         rc = fail(ME_EHIP, "upload of the helicity table failed");
     if (rc == ME_OK && rambo(h, PREPASS_SEED, std::max(sqrt_s, 2.0 * final_mass_sum(h) + 1.0), 0, n, d_mom, st) != hipSuccess)
         rc = fail(ME_EHIP, "pre-pass RAMBO launch failed");
-    if (rc == ME_OK) rc = run_chunks(h, true, d_all, nhel, pchunk, d_mom, n, d_out, d_hel, d_jamp, st);
+    if (rc == ME_OK)
+        rc = run_chunks(h, ME_FP64, d_all, nhel, hpg, groups, pchunk, jamp_per_event, d_mom, n, d_out, d_hel, d_jamp, st);
     if (rc == ME_OK) {
         if (hipMemcpyAsync(out.data(), d_out, n * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipMemcpyAsync(hel.data(), d_hel, hel.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -311,11 +416,16 @@ int helicity_prepass(me_handle* h, hipStream_t st)
             h->h_hel_good.insert(h->h_hel_good.end(), all.begin() + (size_t)hh * npar, all.begin() + (size_t)(hh + 1) * npar);
     h->n_good = (int)(h->h_hel_good.size() / npar);
     if (h->n_good == 0) return fail(ME_EINVAL, "helicity pre-pass found no contributing helicity");
-    if (hipMalloc(&h->d_hel_good, h->h_hel_good.size()) != hipSuccess)
+    std::vector<int> index;
+    for (int hh = 0; hh < nhel; ++hh)
+        if (h->hel_ratio[hh] > PREPASS_THRESHOLD) index.push_back(hh);
+    if (hipMalloc(&h->d_hel_good, h->h_hel_good.size()) != hipSuccess ||
+        hipMalloc(&h->d_hel_index, index.size() * sizeof(int)) != hipSuccess)
         return fail(ME_ENOMEM, "hipMalloc of the helicity list failed");
-    if (hipMemcpy(h->d_hel_good, h->h_hel_good.data(), h->h_hel_good.size(), hipMemcpyHostToDevice) != hipSuccess)
+    if (hipMemcpy(h->d_hel_good, h->h_hel_good.data(), h->h_hel_good.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->d_hel_index, index.data(), index.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
         return fail(ME_EHIP, "upload of the helicity list failed");
-    h->bytes_resident += h->h_hel_good.size();
+    h->bytes_resident += h->h_hel_good.size() + index.size() * sizeof(int);
     return ME_OK;
 }
 
@@ -332,7 +442,10 @@ me_handle* me_create(const char* process, const double* masses, int n_masses, co
     if (!process) { fail(ME_EINVAL, "process is NULL"); return nullptr; }
     const me::ProcessDesc* P = find_process(process);
     if (!P) { fail(ME_ENOPROC, std::string("unknown process: ") + process); return nullptr; }
-    if (precision != ME_FP64 && precision != ME_MIXED_FP16) { fail(ME_EINVAL, "unknown precision"); return nullptr; }
+    if (precision != ME_FP64 && precision != ME_MIXED_FP16 && precision != ME_MIXED_BF16) {
+        fail(ME_EINVAL, "unknown precision");
+        return nullptr;
+    }
     if ((masses && (n_masses < 1 || n_masses > 2)) || (couplings && n_couplings != 2)) {
         fail(ME_EINVAL, "masses: {m_t} or {m_t, w_t}; couplings: {alpha_em, alpha_s}");
         return nullptr;
@@ -366,12 +479,15 @@ me_handle* me_create(const char* process, const double* masses, int n_masses, co
         return nullptr;
     }
     const size_t rsize = (precision == ME_FP64) ? sizeof(double) : sizeof(float);
-    h->bytes_per_event = (size_t)h->n_good * 2 * (P->nc + P->nslot) * rsize;
+    h->jamp_bytes_per_event = (size_t)h->n_good * 2 * (P->nc + P->nslot) * rsize;
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) total_b = size_t(64) << 30;
-    h->scratch_cap = std::max(SCRATCH_MIN, std::min<size_t>(SCRATCH_EVENTS * h->bytes_per_event, total_b / 8));
-    int64_t chunk = (int64_t)(h->scratch_cap / h->bytes_per_event) / 64 * 64;
+    h->scratch_cap = std::max(SCRATCH_MIN, std::min<size_t>(SCRATCH_EVENTS * h->jamp_bytes_per_event, total_b / 8));
+    int64_t chunk = (int64_t)(h->scratch_cap / h->jamp_bytes_per_event) / 64 * 64;
     h->chunk = std::max<int64_t>(64, chunk);
+    // the helicity split is fixed per handle, so an event's result does not depend on the batch
+    helicity_groups(P, h->n_good, h->chunk, &h->groups, &h->hel_per_group);
+    h->bytes_per_event = h->jamp_bytes_per_event + (h->groups > 1 ? h->groups * sizeof(double) : 0);
     return h;
 }
 
@@ -397,6 +513,8 @@ int me_info(const me_handle* h, me_info_t* out)
     out->bytes_resident = (int64_t)h->bytes_resident;
     out->bytes_per_event_scratch = (int64_t)h->bytes_per_event;
     out->chunk_events = h->chunk;
+    out->n_order = P->n_order;
+    out->helicity_groups = h->groups;
     return ME_OK;
 }
 
@@ -427,20 +545,29 @@ int rambo_momenta(const me_handle* h, uint64_t seed, double sqrt_s, int64_t evt0
     return ME_OK;
 }
 
-int me_sigma_hel(me_handle* h, const double* momenta, int64_t n_evt, double* out_me2, double* out_hel, void* stream)
+namespace {
+
+// me_sigma, me_sigma_hel and me_sigma_select: equal chunks through the stream's scratch
+int sigma_impl(me_handle* h, const double* momenta, int64_t n_evt, double* out_me2, double* out_hel,
+               const Selection* sel_in, void* stream)
 {
     if (!h) return fail(ME_EINVAL, "handle is NULL");
     if (n_evt < 0) return fail(ME_EINVAL, "negative event count");
     if (n_evt == 0) return ME_OK;
     if (!is_device_pointer(momenta) || !is_device_pointer(out_me2) || (out_hel && !is_device_pointer(out_hel)))
         return fail(ME_EINVAL, "momenta and outputs must be device pointers");
+    if (sel_in && (!is_device_pointer(sel_in->r_hel) || !is_device_pointer(sel_in->r_col) ||
+                   !is_device_pointer(sel_in->out_hel) || !is_device_pointer(sel_in->out_col)))
+        return fail(ME_EINVAL, "random numbers and choices must be device pointers");
     if (reinterpret_cast<uintptr_t>(momenta) % 16 != 0) return fail(ME_EINVAL, "momenta must be 16-byte aligned");
     hipStream_t st = static_cast<hipStream_t>(stream);
     // equal chunks no larger than the scratch cap allows
     const int64_t n_chunks = (n_evt + h->chunk - 1) / h->chunk;
     const int64_t chunk = ((n_evt + n_chunks - 1) / n_chunks + 63) / 64 * 64;
-    const size_t need = (size_t)chunk * h->bytes_per_event;
-    void* jamp = nullptr;
+    // selection adds |M_h|^2 and the leading-colour weights of one chunk
+    const size_t sel_bytes = sel_in ? (size_t)(h->n_good + h->P->nc) * sizeof(double) : 0;
+    const size_t need = (size_t)chunk * (h->bytes_per_event + sel_bytes);
+    void* scratch = nullptr;
     {
         std::lock_guard<std::mutex> lk(h->mu);
         Scratch& s = h->scratch[st];
@@ -458,10 +585,41 @@ int me_sigma_hel(me_handle* h, const double* momenta, int64_t n_evt, double* out
             }
             s.bytes = want;
         }
-        jamp = s.ptr;
+        scratch = s.ptr;
     }
-    return run_chunks(h, h->precision == ME_FP64, h->d_hel_good, h->n_good, chunk, momenta, n_evt, out_me2, out_hel,
-                      jamp, st, h->profiling);
+    Selection sel{};
+    if (sel_in) {
+        sel = *sel_in;
+        sel.hel_me = reinterpret_cast<double*>(static_cast<char*>(scratch) + (size_t)chunk * h->bytes_per_event);
+        sel.w = sel.hel_me + (size_t)chunk * h->n_good;
+    }
+    return run_chunks(h, h->precision, h->d_hel_good, h->n_good, h->hel_per_group, h->groups, chunk,
+                      h->jamp_bytes_per_event, momenta, n_evt, out_me2, out_hel, scratch, st, h->profiling,
+                      sel_in ? &sel : nullptr);
+}
+
+}  // namespace
+
+int me_sigma_hel(me_handle* h, const double* momenta, int64_t n_evt, double* out_me2, double* out_hel, void* stream)
+{
+    return sigma_impl(h, momenta, n_evt, out_me2, out_hel, nullptr, stream);
+}
+
+int me_sigma_select(me_handle* h, const double* momenta, int64_t n_evt, const double* rnd_hel, const double* rnd_col,
+                    double* out_me2, int* out_hel, int* out_col, void* stream)
+{
+    if (n_evt > 0 && (!rnd_hel || !rnd_col || !out_hel || !out_col))
+        return fail(ME_EINVAL, "random numbers and choices must be given");
+    const Selection sel{rnd_hel, rnd_col, out_hel, out_col, nullptr, nullptr};
+    return sigma_impl(h, momenta, n_evt, out_me2, nullptr, &sel, stream);
+}
+
+int me_colour_flows(const me_handle* h, int* out)
+{
+    if (!h || !out) return fail(ME_EINVAL, "NULL argument");
+    const int no = h->P->n_order;
+    if (no > 0) std::memcpy(out, h->P->orderings, sizeof(int) * h->P->nc * no);
+    return h->P->nc;
 }
 
 int me_profile(me_handle* h, int enable, double* ms_amp, double* ms_colour, int64_t* n_amp, int64_t* n_colour)

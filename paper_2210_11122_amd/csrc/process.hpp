@@ -21,7 +21,8 @@ struct ProcessDesc {
     const int* colour_num;     // nc x nc integer numerators of the colour matrix
     int colour_den;            // their common denominator
     const int* final_massive;  // npar-2 flags: final-state particle carries the top mass
-    const int* orderings;      // nc x (gluons): the gluon order of each colour flow
+    const int* orderings;      // nc x n_order: the gluon order of each colour flow
+    int n_order;               // entries per flow (gluons of the quark line; for gg->gg the three non-root gluons)
     int n_diagrams;            // Feynman diagrams
     int n_amplitudes;          // vertex contractions (four-gluon vertices count 3)
     double flops_lane;         // algorithmic flops of the amplitude kernel per (event, helicity)

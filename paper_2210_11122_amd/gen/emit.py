@@ -56,7 +56,7 @@ class Process:
             self.coupling = "alpha_s"
         # processes too large for one kernel: the diagram program is cut into segments
         # (one kernel each) and the jamps go through a window of LDS slots, written out as
-        # partial sums
+        # partial sums that a reduce kernel adds up
         self.segments = SEGMENTS.get(name)
         self._build()
 
@@ -315,6 +315,7 @@ class Process:
         cn = ", ".join(str(x) for row in self.cnum for x in row)
         masses = ", ".join("1" if m == "m" else "0" for m in self.final_masses)
         perm_flat = ", ".join(str(x) for p in self.perms for x in p) or "0"
+        n_order = len(self.perms[0]) if self.perms else 0
         L = []
         L.append(f"// Generated by paper_2210_11122_amd.gen for the process {nm}; do not edit.")
         L.append(f"// {self.n_diagrams} Feynman diagrams ({self.n_amplitudes} vertex contractions), "
@@ -392,7 +393,8 @@ class Process:
         L.append("    static const ProcessDesc d = {")
         L.append(f'        "{nm}", proc_{nm}::NPAR, proc_{nm}::NC, {1 << self.npar}, '
                  f"{self.avg}, {self.sym}, {1 if self.coupling == 'alpha_s' else 0},")
-        L.append(f"        proc_{nm}::colour_num, {self.cden}, proc_{nm}::final_massive, proc_{nm}::orderings,")
+        L.append(f"        proc_{nm}::colour_num, {self.cden}, proc_{nm}::final_massive, proc_{nm}::orderings, "
+                 f"{n_order},")
         L.append(f"        {self.n_diagrams}, {self.n_amplitudes}, {fl}.0, {self.flops_exec}.0, proc_{nm}::NSLOT,")
         L.append(f"        proc_{nm}::launch<double>, proc_{nm}::launch<float>,")
         L.append("    };")

@@ -109,17 +109,46 @@ def test_rambo_gpu_matches_cpu(name):
     assert np.max(np.abs(g - c)) <= 1e-13 * W.sqrt_s(name)
 
 
+# Mixed-form bars.  Both forms run the amplitudes in FP32 (unit roundoff 6e-8) and split each
+# scaled jamp into two 16-bit terms: 22 significant bits for FP16, 16 for BF16 (relative
+# error per element 2^-23 and 2^-17 of the column's largest jamp).  The colour sum
+# cancels between flows, which multiplies these by the column's condition number; the
+# bars give the FP32 amplitude error (median ~1e-7) a factor 100 and the BF16 split
+# (2^-17 = 7.6e-6) a factor 10 in the median, and allow the soft/collinear tail a p99 of
+# 1e-3 (FP16) or 1e-2 (BF16).
+MIXED_BARS = {"mixed_fp16": (1e-5, 1e-3), "mixed_bf16": (1e-4, 1e-2)}
+
+
+@pytest.mark.parametrize("precision", ["mixed_fp16", "mixed_bf16"])
 @pytest.mark.parametrize("name", ["gg_tt", "gg_ttg", "gg_ttgg", "gg_ttggg"])
-def test_mixed_precision_error_statistics(name):
+def test_mixed_precision_error_statistics(name, precision):
+    print(f"case {precision} {name}", flush=True)
     n = {"gg_tt": 4096, "gg_ttg": 2048, "gg_ttgg": 512, "gg_ttggg": 256}[name]
     p = oracle.rambo(W.SEED, W.sqrt_s(name), W.final_masses(name), n)
     x = torch.from_numpy(p).cuda()
     ref = make_process(name).sigma(x).cpu().numpy()
-    mix = make_process(name, "mixed_fp16").sigma(x).cpu().numpy()
+    mix = make_process(name, precision).sigma(x).cpu().numpy()
     rel = np.abs(mix / ref - 1)
-    print(f"{name} mixed_fp16: max {rel.max():.2e} median {np.median(rel):.2e} "
+    print(f"{name} {precision}: max {rel.max():.2e} median {np.median(rel):.2e} "
           f"p99 {np.quantile(rel, 0.99):.2e}", flush=True)
-    assert np.median(rel) < 1e-5 and np.quantile(rel, 0.99) < 1e-3
+    med, p99 = MIXED_BARS[precision]
+    assert np.median(rel) < med and np.quantile(rel, 0.99) < p99
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_fp16", "mixed_bf16"])
+@pytest.mark.parametrize("name", ["gg_ttgg", "gg_ttggg"])
+def test_result_independent_of_batch(name, precision):
+    """an event's result is bitwise the same alone, at the head of a batch and in its tail
+    (no reduction across events; the colour sum's helicity split is fixed per handle)"""
+    print(f"case batch independence {name} {precision}", flush=True)
+    n = {"gg_ttgg": 5000, "gg_ttggg": 700}[name]
+    p = oracle.rambo(11, W.sqrt_s(name), W.final_masses(name), n)
+    x = torch.from_numpy(p).cuda()
+    proc = make_process(name, precision)
+    full = proc.sigma(x).cpu().numpy()
+    head = proc.sigma(x[:37].contiguous()).cpu().numpy()
+    tail = proc.sigma(x[n - 101:].contiguous()).cpu().numpy()
+    assert np.array_equal(full[:37], head) and np.array_equal(full[n - 101:], tail)
 
 
 def test_large_batch_sampled_parity():
@@ -131,6 +160,25 @@ def test_large_batch_sampled_parity():
     assert proc.info["chunk_events"] < n   # several launches
     got = proc.sigma(torch.from_numpy(p).cuda()).cpu().numpy()
     idx = np.unique(np.concatenate([np.arange(0, n, 4099), [n - 1], np.arange(43000, 43100)]))
+    want = oracle.me_batch(name, p[idx], params=W.PARAMS)
+    rel = np.abs(got[idx] / want - 1)
+    for k in np.where(rel > TOL)[0]:
+        ok, r, spread = referee.judge(name, p[idx[k]], got[idx[k]], W.PARAMS)
+        assert ok, (int(idx[k]), r, spread)
+    assert np.all(np.isfinite(got)) and np.all(got > 0)
+
+
+def test_large_batch_sampled_parity_ttggg():
+    """gg_ttggg at its full configuration size (2^18 events, chunked, as the bench launches
+    it): sampled events, chunk boundaries included, against the oracle one by one"""
+    name, n = "gg_ttggg", 1 << 18
+    p = oracle.rambo(W.SEED, W.sqrt_s(name), W.final_masses(name), n)
+    proc = make_process(name)
+    chunk = proc.info["chunk_events"]
+    assert chunk < n
+    print(f"case gg_ttggg full size, chunk {chunk}", flush=True)
+    got = proc.sigma(torch.from_numpy(p).cuda()).cpu().numpy()
+    idx = np.unique(np.concatenate([np.arange(0, n, 8191), [chunk - 1, chunk, 2 * chunk - 1, n - 1]]))
     want = oracle.me_batch(name, p[idx], params=W.PARAMS)
     rel = np.abs(got[idx] / want - 1)
     for k in np.where(rel > TOL)[0]:

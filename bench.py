@@ -57,13 +57,15 @@ def timed_steps(proc, x, steps, warmup, torch):
 
 
 def kernel_source_hash(process):
-    """hash of the sources that define the amplitude kernel of `process`"""
+    """hash of the sources that define the amplitude kernel of `process` and its launch (the
+    helper header and the generated file up to the process descriptor)"""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2210_11122_amd", "csrc")
     h = hashlib.sha256()
-    for f in ["helas.hpp", os.path.join("generated", f"proc_{process}.hip")]:
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
+    with open(os.path.join(csrc, "helas.hpp"), "rb") as fh:
+        h.update(fh.read())
+    with open(os.path.join(csrc, "generated", f"proc_{process}.hip"), "rb") as fh:
+        h.update(fh.read().split(b"const ProcessDesc* process_")[0])
     return h.hexdigest()[:16]
 
 

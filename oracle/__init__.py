@@ -46,6 +46,7 @@ def _load(name):
     lib.or_colour_matrix.argtypes = [ctypes.c_int, _D]
     lib.or_colour_matrix_methods.argtypes = [ctypes.c_int, _D, _D]
     lib.or_amp_explicit_colour.argtypes = [ctypes.c_int, _D, _D, ctypes.c_int, _I, _D, _D]
+    lib.or_tree_amp.argtypes = [ctypes.c_int, _D, _D, ctypes.c_int, _I, ctypes.c_int, _D]
     lib.or_me_brute_colour.restype = ctypes.c_double
     lib.or_me_brute_colour.argtypes = [ctypes.c_int, _D, _D]
     lib.or_spin_sums.argtypes = [_D, ctypes.c_double, ctypes.c_int, _D, _D, _D]

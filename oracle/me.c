@@ -991,6 +991,95 @@ int or_amp_explicit_colour(int proc, const double *params, const double *p, int 
     return 0;
 }
 
+/* Colour-stripped amplitude of ONE Feynman diagram of a quark-line process, helicity h
+ * (for the single-diagram channel weights).  The diagram is a postfix program:
+ *   op >= 0      push gluon op's polarisation (gluons counted in particle order)
+ *   op == -1     pop B, pop A, push the three-gluon current  g V(A, B) (-i / P^2)
+ *                (the Lorentz part of g f^{abc}[..] with a off-shell, b = A, c = B)
+ *   op == -2-s   pop C, B, A, push the four-gluon current of colour structure s = 0, 1, 2:
+ *                -i g^2 L_s(A, B, C) (-i / P^2), L_0 = B(A.C) - C(A.B), L_1 = A(B.C) - C(A.B),
+ *                L_2 = A(B.C) - B(A.C), paired with f^{abe}f^{cde}, f^{ace}f^{bde}, f^{ade}f^{bce}
+ *   op == -10-k  the k currents on top of the stack are the quark-line attachments G_1..G_k
+ *                (G_1 pushed first, nearest the antiquark): out = ubar (i g gamma.G_k) S ...
+ *                S (i g gamma.G_1) v, S(q) = i (qslash + m)/(q^2 - m^2); colour factor
+ *                (t^{a_k} .. t^{a_1})_{ij} stripped.  Must be the last op.
+ * Each current carries its summed incoming momentum.  Returns 0, or -1 on a malformed
+ * program. */
+int or_tree_amp(int proc, const double *params, const double *p, int h, const int *prog, int len,
+                double *out)
+{
+    if (proc <= P_EE_MUMU || proc >= P_GG_GG) return -1;
+    tables();
+    real par[3];
+    load_par(params, par);
+    ext_t X;
+    setup_qcd(proc, p, par, h, 0, &X);
+    real g = X.g;
+    cplx J[16][4];
+    real P[16][4];
+    int sp = 0;
+    for (int t = 0; t < len; ++t) {
+        int op = prog[t];
+        if (op >= 0) {
+            if (op >= X.ng || sp >= 16) return -1;
+            memcpy(J[sp], X.e[op], sizeof J[sp]);
+            memcpy(P[sp], X.q[op], sizeof P[sp]);
+            ++sp;
+        } else if (op == -1) {
+            if (sp < 2) return -1;
+            cplx V[4];
+            real Q[4];
+            vvv(J[sp - 2], P[sp - 2], J[sp - 1], P[sp - 1], V);
+            for (int mu = 0; mu < 4; ++mu) Q[mu] = P[sp - 2][mu] + P[sp - 1][mu];
+            cplx f = -I / dot_rr(Q, Q);
+            sp -= 2;
+            for (int mu = 0; mu < 4; ++mu) {
+                J[sp][mu] = f * g * V[mu];
+                P[sp][mu] = Q[mu];
+            }
+            ++sp;
+        } else if (op >= -4) {
+            if (sp < 3) return -1;
+            int s = -2 - op;
+            const cplx *A = J[sp - 3], *B = J[sp - 2], *C = J[sp - 1];
+            cplx ab = dot_cc(A, B), ac = dot_cc(A, C), bc = dot_cc(B, C), L[4];
+            real Q[4];
+            for (int mu = 0; mu < 4; ++mu) {
+                if (s == 0) L[mu] = B[mu] * ac - C[mu] * ab;
+                else if (s == 1) L[mu] = A[mu] * bc - C[mu] * ab;
+                else L[mu] = A[mu] * bc - B[mu] * ac;
+                Q[mu] = P[sp - 3][mu] + P[sp - 2][mu] + P[sp - 1][mu];
+            }
+            cplx f = -I / dot_rr(Q, Q);
+            sp -= 3;
+            for (int mu = 0; mu < 4; ++mu) {
+                J[sp][mu] = f * (-I * g * g) * L[mu];
+                P[sp][mu] = Q[mu];
+            }
+            ++sp;
+        } else {
+            int k = -10 - op;
+            if (k < 1 || k != sp || t != len - 1) return -1;
+            cplx psi[4], tmp[4];
+            memcpy(psi, X.v, sizeof psi);
+            real q[4];
+            for (int mu = 0; mu < 4; ++mu) q[mu] = -X.pa[mu];
+            for (int a = 0; a < k; ++a) {
+                vertex_q(J[a], g, psi, tmp);
+                if (a == k - 1) {
+                    cplx r = rowcol(X.ubar, tmp);
+                    out[0] = (double)creal(r);
+                    out[1] = (double)cimag(r);
+                    return 0;
+                }
+                for (int mu = 0; mu < 4; ++mu) q[mu] += P[a][mu];
+                prop_q(q, X.m, tmp, psi);
+            }
+        }
+    }
+    return -1;
+}
+
 /* Brute force: averaged sum over all helicities and ALL explicit colour assignments of
  * |M|^2 from the colour-dressed recursion (no colour matrix, no decomposition). */
 double or_me_brute_colour(int proc, const double *params, const double *p)

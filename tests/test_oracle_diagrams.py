@@ -1,0 +1,58 @@
+"""Pins of the oracle's single-diagram machinery (oracle/diagrams.py), used for the
+single-diagram-enhancement channel weights:
+
+* diagram and amplitude-entry counts 3/16/123/1240 and 3/18/159/1890 (the published
+  diagram counts of gg -> t t~ + 0..3 g; a four-gluon vertex has three colour structures);
+* colour weights of gg -> t t~: t- and u-channel diagrams (t^a t^b)_{ij}: Tr(t^a t^b t^b t^a)
+  = N C_F^2 = 16/3; s-channel f^{abc} t^c: C_A (N^2 - 1) / 2 = 12;
+* completeness: the coherent sum over every diagram and colour structure, squared and
+  summed over explicit colours and helicities, equals the Berends-Giele |M|^2 (an
+  independent algorithm, itself pinned by the closed forms);
+* the channel weights of an event sum to one.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import diagrams as Dg
+from tests import workloads as W
+
+
+@pytest.mark.parametrize("ng,nd,ne", [(2, 3, 3), (3, 16, 18), (4, 123, 159), (5, 1240, 1890)])
+def test_diagram_counts(ng, nd, ne):
+    ds = Dg.diagrams(ng)
+    assert len(ds) == nd
+    assert sum(len(Dg.structures(d)) for d in ds) == ne
+    name = {2: "gg_tt", 3: "gg_ttg", 4: "gg_ttgg", 5: "gg_ttggg"}[ng]
+    assert len({Dg.descriptor(name, d) for d in ds}) == nd     # internal lines identify a diagram
+
+
+def test_gg_tt_colour_weights():
+    K = Dg.colour_weights_K("gg_tt")
+    by = {Dg.descriptor("gg_tt", d): k for (d, s), k in zip(Dg.entries("gg_tt"), K)}
+    # particles (g0, g1, t, t~): t-channel line {1, 2}, u-channel {1, 3}, s-channel gluon {2, 3}
+    assert by[(0b0110,)] == pytest.approx(16 / 3, rel=1e-14)
+    assert by[(0b1010,)] == pytest.approx(16 / 3, rel=1e-14)
+    assert by[(0b1100,)] == pytest.approx(12.0, rel=1e-14)
+
+
+@pytest.mark.parametrize("name", ["gg_tt", "gg_ttg", "gg_ttgg"])
+def test_coherent_sum_of_diagrams_is_the_matrix_element(name):
+    ng = oracle.n_par(name) - 2
+    ents = Dg.entries(name)
+    CF = np.array([Dg.colour_tensor(d, s, ng).ravel() for d, s in ents])
+    p = oracle.rambo(3, 1500.0, W.final_masses(name), 1)[0]
+    tot = 0.0
+    for h in range(1 << oracle.n_par(name)):
+        L = np.array([Dg.lorentz(name, p, h, d, s, W.PARAMS) for d, s in ents])
+        tot += np.sum(np.abs(L @ CF) ** 2)
+    assert tot / 256 == pytest.approx(oracle.me(name, p, params=W.PARAMS), rel=1e-12)
+
+
+@pytest.mark.parametrize("name", ["gg_tt", "gg_ttg"])
+def test_channel_weights_sum_to_one(name):
+    p = oracle.rambo(4, 1500.0, W.final_masses(name), 1)[0]
+    Wd = Dg.diagram_weights(name, p, W.PARAMS)
+    assert len(Wd) == {"gg_tt": 3, "gg_ttg": 16}[name]
+    f = np.array(list(Wd.values())) / sum(Wd.values())
+    assert np.all(f > 0) and f.sum() == pytest.approx(1.0, rel=1e-14)

@@ -224,3 +224,15 @@ def test_batch_matches_single():
     b = oracle.me_batch("gg_ttg", p, threads=3)
     for i in range(24):
         assert b[i] == oracle.me("gg_ttg", p[i])
+
+
+@pytest.mark.parametrize("name", ["gg_tt", "gg_ttg", "gg_ttgg"])
+def test_oracle_alpha_s_power(name):
+    """every tree amplitude of these processes has n_par - 2 strong couplings: the oracle,
+    which recomputes every vertex at the given alpha_s, scales as alpha_s^(n_par - 2)"""
+    p = oracle.rambo(5, 1500.0, W.final_masses(name), 2)
+    n = oracle.n_par(name) - 2
+    for ev in p:
+        a = oracle.me(name, ev, params=(W.M_TOP, W.ALPHA_EM, 0.118))
+        b = oracle.me(name, ev, params=(W.M_TOP, W.ALPHA_EM, 0.2))
+        assert b / a == pytest.approx((0.2 / 0.118) ** n, rel=1e-12)

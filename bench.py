@@ -87,6 +87,44 @@ def quantile(v, q):
     return float(np.quantile(np.asarray(v), q)) if len(v) else None
 
 
+def sweep(processes, precisions, log2_sizes, torch, min_ms=300.0):
+    """batch-size sweep: median per-call time (HIP events) of me_sigma per process, precision
+    and batch size, momenta resident on the device"""
+    import numpy as np
+    from paper_2210_11122_amd import Process
+    from tests import workloads as W
+    out = {}
+    for name in processes:
+        rows = []
+        for prec in precisions:
+            proc = Process(name, m_top=W.M_TOP, alpha_em=W.ALPHA_EM, alpha_s=W.ALPHA_S, precision=prec)
+            for k in log2_sizes(name):
+                n = 1 << k
+                x = proc.rambo(W.SEED, W.sqrt_s(name), n)
+                y = torch.empty(n, dtype=torch.float64, device="cuda")
+                for _ in range(2):
+                    proc.sigma(x, out=y)
+                torch.cuda.synchronize()
+                times, spent = [], 0.0
+                while len(times) < 5 or (spent < min_ms and len(times) < 200):
+                    a = torch.cuda.Event(enable_timing=True)
+                    b = torch.cuda.Event(enable_timing=True)
+                    a.record()
+                    proc.sigma(x, out=y)
+                    b.record()
+                    b.synchronize()
+                    times.append(a.elapsed_time(b))
+                    spent += times[-1]
+                med = float(np.median(times))
+                rows.append({"precision": prec, "n_evt": n, "ms_median": med, "MEs_per_s": n / med * 1e3,
+                             "calls": len(times)})
+                log(f"sweep {name} {prec} n=2^{k}: {med:.4f} ms, {n / med * 1e3:.4g} MEs/s")
+                del x, y
+            del proc
+        out[name] = rows
+    return out
+
+
 def cpu_baseline(name, n_evt_total, params, budget_s, threads):
     """the oracle as it stands on a bounded sample: first events of the same RAMBO stream"""
     import numpy as np
@@ -121,12 +159,16 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--sweep", action="store_true",
+                    help="batch-size sweep 2^8..2^20 of every process instead of the benchmark line")
+    ap.add_argument("--serving-processes", default="gg_tt,gg_ttg,gg_ttgg")
+    ap.add_argument("--serving-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run one plain device copy of this size (for PMC byte calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); the events are independent and the "
-              "a run on N GPUs would give each GPU 1/N of the events; it is not measured here.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the events are independent, so a run "
+              "on N GPUs would give each GPU 1/N of the events; it is not measured here.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -138,6 +180,12 @@ def main():
     n_evt = args.n_evt or W.PROCESSES[name][2]
     rs = W.sqrt_s(name)
     torch.cuda.set_device(0)
+    if args.sweep:
+        sizes = lambda nm: range(8, (19 if nm == "gg_ttggg" else 21), 2)
+        res = sweep(["ee_mumu", "gg_tt", "gg_ttg", "gg_ttgg", "gg_ttggg"], ["fp64", "mixed_fp16"], sizes, torch)
+        print(json.dumps({"metric": "batch-size sweep: matrix elements/sec at 1 GPU", "unit": "MEs/s",
+                          "data": "synthetic (RAMBO phase space on device, seed 0)", "sweep": res}), flush=True)
+        return
     log(f"bench: {name} n_evt={n_evt} steps={args.steps} warmup={args.warmup}")
 
     p64 = Process(name, m_top=W.M_TOP, alpha_em=W.ALPHA_EM, alpha_s=W.ALPHA_S, precision="fp64")
@@ -227,7 +275,8 @@ def main():
     if not args.no_serving:
         try:
             from paper_2210_11122_amd import serve
-            result["serving"] = serve.bench_serving(duration_s=10.0, log=log)
+            result["serving"] = serve.bench_serving(duration_s=args.serving_seconds,
+                                                    processes=tuple(args.serving_processes.split(",")), log=log)
         except ImportError:
             result["serving"] = None
 
@@ -245,8 +294,14 @@ def main():
             referee_ok += ok
             worst.append((r, spread, int(i)))
         worst.sort(reverse=True)
+        import oracle
+        n1 = max(1, min(len(p), int(rate / threads * 2.0)))
+        t1 = time.perf_counter()
+        oracle.me_batch(name, p[:n1], params=W.PARAMS, threads=1)
+        rate1 = n1 / (time.perf_counter() - t1)
         result["cpu_baseline"] = {"value": rate, "unit": "MEs/s", "cores": threads, "kind": "oracle",
-                                  "sample": f"first {len(p)} events of the same RAMBO stream, {dt:.1f} s"}
+                                  "sample": f"first {len(p)} events of the same RAMBO stream, {dt:.1f} s",
+                                  "single_thread_value": rate1, "single_thread_sample": f"first {n1} events"}
         result["parity_sample"] = {"n": int(len(p)), "max_rel_err": float(rel.max()),
                                    "median_rel_err": float(np.median(rel)), "tolerance": 1e-12,
                                    "n_over_tolerance": int(len(over)),

@@ -88,6 +88,15 @@ int me_sigma_hel(me_handle *h, const double *momenta, int64_t n_evt, double *out
 int me_sigma_select(me_handle *h, const double *momenta, int64_t n_evt, const double *rnd_hel,
                     const double *rnd_col, double *out_me2, int *out_hel, int *out_col, void *stream);
 
+/* As me_sigma with a strong coupling per event (the "running" alpha_s of the paper, Sec. 2):
+ * alpha_s_evt = DEVICE double[n_evt], alpha_s at each event's renormalisation scale, chosen and
+ * evaluated by the caller.  Exact for these tree-level QCD processes: |M|^2 is homogeneous of
+ * degree n_par - 2 in alpha_s, so the library evaluates the amplitudes at the handle's alpha_s
+ * and multiplies by (alpha_s_evt[e] / alpha_s)^(n_par - 2).  No effect for ee_mumu (QED).
+ * ME_EINVAL for NULL or host pointers. */
+int me_sigma_alphas(me_handle *h, const double *momenta, int64_t n_evt, const double *alpha_s_evt,
+                    double *out_me2, void *stream);
+
 /* colour flows: out[k * n_order + j] = the j-th gluon (0 = first gluon of the process) in
  * the ordering of flow k, n_order = gluons on the quark line (gg_gg: the three gluons after
  * gluon 3, which closes the trace; ee_mumu: 0).  out must hold n_colors * n_order ints.

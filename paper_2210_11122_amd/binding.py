@@ -34,7 +34,7 @@ class MeInfo(ctypes.Structure):
 
 
 EXPORTS = ["me_create", "me_destroy", "me_info", "me_last_error", "rambo_momenta", "me_sigma",
-           "me_sigma_hel", "me_sigma_select", "me_colour_flows", "me_good_helicities", "me_helicity_ratios",
+           "me_sigma_hel", "me_sigma_select", "me_sigma_alphas", "me_colour_flows", "me_good_helicities", "me_helicity_ratios",
            "me_profile"]
 
 _lib = None
@@ -59,6 +59,7 @@ def load():
     L.me_sigma_hel.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp]
     L.me_sigma_select.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp, vp, vp, vp]
     L.me_colour_flows.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+    L.me_sigma_alphas.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp]
     L.me_good_helicities.argtypes = [vp, ctypes.POINTER(ctypes.c_byte)]
     L.me_helicity_ratios.argtypes = [vp, D]
     L.me_profile.argtypes = [vp, ctypes.c_int, D, D, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
@@ -156,6 +157,20 @@ class Process:
                                       ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(hel.data_ptr()),
                                       ctypes.c_void_p(col.data_ptr()), _stream_ptr(stream)), "me_sigma_select")
         return out, hel, col
+
+    def sigma_alphas(self, momenta, alpha_s, out=None, stream=None):
+        """averaged |M|^2 with the strong coupling alpha_s[e] (device float64 [n_evt]) per event"""
+        import torch
+        assert momenta.is_cuda and momenta.dtype == torch.float64 and momenta.is_contiguous()
+        n = momenta.shape[0]
+        assert momenta.shape[1:] == (self.n_par, 4)
+        assert alpha_s.is_cuda and alpha_s.dtype == torch.float64 and alpha_s.is_contiguous() and alpha_s.shape == (n,)
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=momenta.device)
+        _check(load().me_sigma_alphas(self._h, ctypes.c_void_p(momenta.data_ptr()), n,
+                                      ctypes.c_void_p(alpha_s.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                      _stream_ptr(stream)), "me_sigma_alphas")
+        return out
 
     def colour_flows(self):
         """gluon ordering of every colour flow (list of tuples, flow order of the jamps)"""

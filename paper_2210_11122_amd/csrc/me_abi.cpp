@@ -234,6 +234,20 @@ struct TimedLaunch {
 };
 
 // amplitude kernel + colour sum for events [0, n) of `mom`, in chunks through `jamp`
+// per-event strong coupling: every tree amplitude of a pure-QCD process carries g_s^(n_par - 2)
+// (a three-gluon or quark-gluon vertex one power, the four-gluon vertex two), so |M|^2 computed
+// at the handle's alpha_s becomes the per-event value through the factor (a_e / a_0)^(n_par - 2)
+__global__ __launch_bounds__(256) void scale_alphas(double* __restrict__ out, const double* __restrict__ alphas,
+                                                    double inv_alpha0, int power, int64_t n)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    const double r = alphas[e] * inv_alpha0;
+    double f = 1.0;
+    for (int k = 0; k < power; ++k) f *= r;
+    out[e] *= f;
+}
+
 // per-event helicity and colour-flow draws (select.hpp); hel_me and w are chunk scratch
 struct Selection {
     const double *r_hel, *r_col;
@@ -244,7 +258,8 @@ struct Selection {
 // scratch: jamps of `chunk` events (jamp_bytes_per_event each), then the helicity-group partial sums
 int run_chunks(me_handle* h, int precision, const signed char* hel, int n_good, int hel_per_group, int groups,
                int64_t chunk, size_t jamp_bytes_per_event, const double* mom, int64_t n, double* out, double* out_hel,
-               void* scratch, hipStream_t st, bool timed = false, const Selection* sel = nullptr)
+               void* scratch, hipStream_t st, bool timed = false, const Selection* sel = nullptr,
+               const double* alphas = nullptr)
 {
     const me::ProcessDesc* P = h->P;
     const bool fp64 = precision == ME_FP64;
@@ -264,6 +279,12 @@ int run_chunks(me_handle* h, int precision, const signed char* hel, int n_good, 
         e = colour_sum(h, precision, jamp, ld, n_good, hel_per_group, groups, nc, out + c0, oh, part, st);
         tc.done();
         if (e != hipSuccess) return fail(ME_EHIP, std::string("colour-sum kernel: ") + hipGetErrorString(e));
+        if (alphas && P->coupling == 1) {
+            hipLaunchKernelGGL(scale_alphas, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, out + c0,
+                               alphas + c0, 1.0 / h->alpha_s, P->npar - 2, nc);
+            e = hipGetLastError();
+            if (e != hipSuccess) return fail(ME_EHIP, std::string("coupling kernel: ") + hipGetErrorString(e));
+        }
         if (sel) {
             const dim3 grid((unsigned)((nc + 255) / 256), (unsigned)P->nc);
             if (fp64)
@@ -549,7 +570,7 @@ namespace {
 
 // me_sigma, me_sigma_hel and me_sigma_select: equal chunks through the stream's scratch
 int sigma_impl(me_handle* h, const double* momenta, int64_t n_evt, double* out_me2, double* out_hel,
-               const Selection* sel_in, void* stream)
+               const Selection* sel_in, void* stream, const double* alphas = nullptr)
 {
     if (!h) return fail(ME_EINVAL, "handle is NULL");
     if (n_evt < 0) return fail(ME_EINVAL, "negative event count");
@@ -559,6 +580,7 @@ int sigma_impl(me_handle* h, const double* momenta, int64_t n_evt, double* out_m
     if (sel_in && (!is_device_pointer(sel_in->r_hel) || !is_device_pointer(sel_in->r_col) ||
                    !is_device_pointer(sel_in->out_hel) || !is_device_pointer(sel_in->out_col)))
         return fail(ME_EINVAL, "random numbers and choices must be device pointers");
+    if (alphas && !is_device_pointer(alphas)) return fail(ME_EINVAL, "alpha_s must be a device pointer");
     if (reinterpret_cast<uintptr_t>(momenta) % 16 != 0) return fail(ME_EINVAL, "momenta must be 16-byte aligned");
     hipStream_t st = static_cast<hipStream_t>(stream);
     // equal chunks no larger than the scratch cap allows
@@ -595,7 +617,7 @@ int sigma_impl(me_handle* h, const double* momenta, int64_t n_evt, double* out_m
     }
     return run_chunks(h, h->precision, h->d_hel_good, h->n_good, h->hel_per_group, h->groups, chunk,
                       h->jamp_bytes_per_event, momenta, n_evt, out_me2, out_hel, scratch, st, h->profiling,
-                      sel_in ? &sel : nullptr);
+                      sel_in ? &sel : nullptr, alphas);
 }
 
 }  // namespace
@@ -612,6 +634,13 @@ int me_sigma_select(me_handle* h, const double* momenta, int64_t n_evt, const do
         return fail(ME_EINVAL, "random numbers and choices must be given");
     const Selection sel{rnd_hel, rnd_col, out_hel, out_col, nullptr, nullptr};
     return sigma_impl(h, momenta, n_evt, out_me2, nullptr, &sel, stream);
+}
+
+int me_sigma_alphas(me_handle* h, const double* momenta, int64_t n_evt, const double* alpha_s_evt, double* out_me2,
+                    void* stream)
+{
+    if (n_evt > 0 && !alpha_s_evt) return fail(ME_EINVAL, "alpha_s_evt must be given");
+    return sigma_impl(h, momenta, n_evt, out_me2, nullptr, nullptr, stream, alpha_s_evt);
 }
 
 int me_colour_flows(const me_handle* h, int* out)

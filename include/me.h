@@ -97,6 +97,23 @@ int me_sigma_select(me_handle *h, const double *momenta, int64_t n_evt, const do
 int me_sigma_alphas(me_handle *h, const double *momenta, int64_t n_evt, const double *alpha_s_evt,
                     double *out_me2, void *stream);
 
+/* As me_sigma, multiplied by the single-diagram-enhancement weight of each event's channel
+ * (MadEvent's multichannel algorithm, which the paper, Sec. 2, lists among the features of
+ * its ME engine): channel = DEVICE int32[n_evt], a Feynman-diagram index in [0, n_diagrams)
+ * (me_diagrams gives each diagram's internal lines), or -1 for no weight.
+ *   out_me2[e] = |M|^2 * W_c / sum_d W_d,  W_d = sum over good helicities and over the diagram's
+ *   four-gluon colour structures of the colour-summed square of that single diagram.
+ * The weights of all channels of an event sum to 1.  An id >= n_diagrams gives 0.
+ * ME_EINVAL for NULL or host pointers, or gg_gg (no channel weights). */
+int me_sigma_channel(me_handle *h, const double *momenta, int64_t n_evt, const int *channel,
+                     double *out_me2, void *stream);
+
+/* The Feynman diagrams: out[d * lines_per_diagram + j] = j-th internal line of diagram d as a
+ * mask of external particles (bit i = particle i, the side without particle 0), ascending,
+ * 0-padded (me_info: lines_per_diagram).  out must hold n_diagrams * lines_per_diagram ints.
+ * Returns n_diagrams, or ME_EINVAL for gg_gg. */
+int me_diagrams(const me_handle *h, int *out);
+
 /* colour flows: out[k * n_order + j] = the j-th gluon (0 = first gluon of the process) in
  * the ordering of flow k, n_order = gluons on the quark line (gg_gg: the three gluons after
  * gluon 3, which closes the trace; ee_mumu: 0).  out must hold n_colors * n_order ints.
@@ -115,6 +132,7 @@ typedef struct {
     int64_t chunk_events;      /* events per amplitude/colour-sum launch pair */
     int n_order;               /* entries per colour flow in me_colour_flows */
     int helicity_groups;       /* colour-sum launches split the good helicities into this many groups */
+    int lines_per_diagram;     /* entries per diagram in me_diagrams */
 } me_info_t;
 
 int me_info(const me_handle *h, me_info_t *out);

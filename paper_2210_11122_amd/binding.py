@@ -27,14 +27,15 @@ class MeInfo(ctypes.Structure):
                 ("flops_amp_lane", ctypes.c_double), ("flops_amp_exec_lane", ctypes.c_double),
                 ("n_partial_slots", ctypes.c_int), ("flops_colour_lane", ctypes.c_double),
                 ("bytes_resident", ctypes.c_int64), ("bytes_per_event_scratch", ctypes.c_int64),
-                ("chunk_events", ctypes.c_int64), ("n_order", ctypes.c_int), ("helicity_groups", ctypes.c_int)]
+                ("chunk_events", ctypes.c_int64), ("n_order", ctypes.c_int), ("helicity_groups", ctypes.c_int),
+                ("lines_per_diagram", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 EXPORTS = ["me_create", "me_destroy", "me_info", "me_last_error", "rambo_momenta", "me_sigma",
-           "me_sigma_hel", "me_sigma_select", "me_sigma_alphas", "me_colour_flows", "me_good_helicities", "me_helicity_ratios",
+           "me_sigma_hel", "me_sigma_select", "me_sigma_alphas", "me_sigma_channel", "me_diagrams", "me_colour_flows", "me_good_helicities", "me_helicity_ratios",
            "me_profile"]
 
 _lib = None
@@ -60,6 +61,8 @@ def load():
     L.me_sigma_select.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp, vp, vp, vp]
     L.me_colour_flows.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     L.me_sigma_alphas.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp]
+    L.me_sigma_channel.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp]
+    L.me_diagrams.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     L.me_good_helicities.argtypes = [vp, ctypes.POINTER(ctypes.c_byte)]
     L.me_helicity_ratios.argtypes = [vp, D]
     L.me_profile.argtypes = [vp, ctypes.c_int, D, D, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
@@ -171,6 +174,31 @@ class Process:
                                       ctypes.c_void_p(alpha_s.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                       _stream_ptr(stream)), "me_sigma_alphas")
         return out
+
+    def sigma_channel(self, momenta, channel, out=None, stream=None):
+        """averaged |M|^2 times the single-diagram weight of channel[e] (device int32 [n_evt],
+        -1: none)"""
+        import torch
+        assert momenta.is_cuda and momenta.dtype == torch.float64 and momenta.is_contiguous()
+        n = momenta.shape[0]
+        assert momenta.shape[1:] == (self.n_par, 4)
+        assert channel.is_cuda and channel.dtype == torch.int32 and channel.is_contiguous() and channel.shape == (n,)
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=momenta.device)
+        _check(load().me_sigma_channel(self._h, ctypes.c_void_p(momenta.data_ptr()), n,
+                                       ctypes.c_void_p(channel.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                       _stream_ptr(stream)), "me_sigma_channel")
+        return out
+
+    def diagrams(self):
+        """internal lines of every Feynman diagram (tuples of particle masks, side without particle 0)"""
+        k = self.info["lines_per_diagram"]
+        nd = self.info["n_diagrams"]
+        buf = (ctypes.c_int * (nd * k))()
+        n = load().me_diagrams(self._h, buf)
+        if n < 0:
+            raise MeError(f"me_diagrams failed: {last_error()}")
+        return [tuple(x for x in buf[d * k:(d + 1) * k] if x) for d in range(n)]
 
     def colour_flows(self):
         """gluon ordering of every colour flow (list of tuples, flow order of the jamps)"""

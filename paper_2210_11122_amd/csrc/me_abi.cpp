@@ -248,6 +248,21 @@ __global__ __launch_bounds__(256) void scale_alphas(double* __restrict__ out, co
     out[e] *= f;
 }
 
+// single-diagram enhancement: out[e] *= (sum_h W_chan,h) / (sum_h sum_d W_d,h) from the
+// per-lane sums sde[h][0: channel, 1: all][column] of the amplitude kernel; chan[e] < 0: no factor
+__global__ __launch_bounds__(256) void sde_apply(double* __restrict__ out, const double* __restrict__ sde,
+                                                 const int* __restrict__ chan, int n_good, int64_t ld, int64_t n)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n || chan[e] < 0) return;
+    double num = 0.0, den = 0.0;
+    for (int h = 0; h < n_good; ++h) {
+        num += sde[(int64_t)(2 * h) * ld + e];
+        den += sde[(int64_t)(2 * h + 1) * ld + e];
+    }
+    out[e] *= num / den;
+}
+
 // per-event helicity and colour-flow draws (select.hpp); hel_me and w are chunk scratch
 struct Selection {
     const double *r_hel, *r_col;
@@ -259,7 +274,7 @@ struct Selection {
 int run_chunks(me_handle* h, int precision, const signed char* hel, int n_good, int hel_per_group, int groups,
                int64_t chunk, size_t jamp_bytes_per_event, const double* mom, int64_t n, double* out, double* out_hel,
                void* scratch, hipStream_t st, bool timed = false, const Selection* sel = nullptr,
-               const double* alphas = nullptr)
+               const double* alphas = nullptr, const int* chan = nullptr, double* sde = nullptr)
 {
     const me::ProcessDesc* P = h->P;
     const bool fp64 = precision == ME_FP64;
@@ -270,8 +285,9 @@ int run_chunks(me_handle* h, int precision, const signed char* hel, int n_good, 
         const int64_t ld = (nc + 63) / 64 * 64;
         const double* m = mom + c0 * P->npar * 4;
         TimedLaunch ta(h, st, 0, timed);
-        hipError_t e = fp64 ? P->launch_f64(m, nc, ld, hel, n_good, h->mt, h->g, static_cast<double*>(jamp), st)
-                            : P->launch_f32(m, nc, ld, hel, n_good, h->mt, h->g, static_cast<float*>(jamp), st);
+        const int* ch = chan ? chan + c0 : nullptr;
+        hipError_t e = fp64 ? P->launch_f64(m, nc, ld, hel, n_good, h->mt, h->g, static_cast<double*>(jamp), ch, sde, st)
+                            : P->launch_f32(m, nc, ld, hel, n_good, h->mt, h->g, static_cast<float*>(jamp), ch, sde, st);
         ta.done();
         if (e != hipSuccess) return fail(ME_EHIP, std::string("amplitude kernel: ") + hipGetErrorString(e));
         TimedLaunch tc(h, st, 1, timed);
@@ -279,6 +295,12 @@ int run_chunks(me_handle* h, int precision, const signed char* hel, int n_good, 
         e = colour_sum(h, precision, jamp, ld, n_good, hel_per_group, groups, nc, out + c0, oh, part, st);
         tc.done();
         if (e != hipSuccess) return fail(ME_EHIP, std::string("colour-sum kernel: ") + hipGetErrorString(e));
+        if (chan) {
+            hipLaunchKernelGGL(sde_apply, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, out + c0, sde, ch,
+                               n_good, ld, nc);
+            e = hipGetLastError();
+            if (e != hipSuccess) return fail(ME_EHIP, std::string("channel-weight kernel: ") + hipGetErrorString(e));
+        }
         if (alphas && P->coupling == 1) {
             hipLaunchKernelGGL(scale_alphas, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, out + c0,
                                alphas + c0, 1.0 / h->alpha_s, P->npar - 2, nc);
@@ -536,6 +558,7 @@ int me_info(const me_handle* h, me_info_t* out)
     out->chunk_events = h->chunk;
     out->n_order = P->n_order;
     out->helicity_groups = h->groups;
+    out->lines_per_diagram = P->lines_per_diagram;
     return ME_OK;
 }
 
@@ -570,7 +593,7 @@ namespace {
 
 // me_sigma, me_sigma_hel and me_sigma_select: equal chunks through the stream's scratch
 int sigma_impl(me_handle* h, const double* momenta, int64_t n_evt, double* out_me2, double* out_hel,
-               const Selection* sel_in, void* stream, const double* alphas = nullptr)
+               const Selection* sel_in, void* stream, const double* alphas = nullptr, const int* chan = nullptr)
 {
     if (!h) return fail(ME_EINVAL, "handle is NULL");
     if (n_evt < 0) return fail(ME_EINVAL, "negative event count");
@@ -581,6 +604,8 @@ int sigma_impl(me_handle* h, const double* momenta, int64_t n_evt, double* out_m
                    !is_device_pointer(sel_in->out_hel) || !is_device_pointer(sel_in->out_col)))
         return fail(ME_EINVAL, "random numbers and choices must be device pointers");
     if (alphas && !is_device_pointer(alphas)) return fail(ME_EINVAL, "alpha_s must be a device pointer");
+    if (chan && !is_device_pointer(chan)) return fail(ME_EINVAL, "channel ids must be a device pointer");
+    if (chan && !h->P->sde_supported) return fail(ME_EINVAL, "no single-diagram channel weights for this process");
     if (reinterpret_cast<uintptr_t>(momenta) % 16 != 0) return fail(ME_EINVAL, "momenta must be 16-byte aligned");
     hipStream_t st = static_cast<hipStream_t>(stream);
     // equal chunks no larger than the scratch cap allows
@@ -588,7 +613,9 @@ int sigma_impl(me_handle* h, const double* momenta, int64_t n_evt, double* out_m
     const int64_t chunk = ((n_evt + n_chunks - 1) / n_chunks + 63) / 64 * 64;
     // selection adds |M_h|^2 and the leading-colour weights of one chunk
     const size_t sel_bytes = sel_in ? (size_t)(h->n_good + h->P->nc) * sizeof(double) : 0;
-    const size_t need = (size_t)chunk * (h->bytes_per_event + sel_bytes);
+    // channel weights add two sums per (event, helicity)
+    const size_t sde_bytes = chan ? (size_t)2 * h->n_good * sizeof(double) : 0;
+    const size_t need = (size_t)chunk * (h->bytes_per_event + sel_bytes + sde_bytes);
     void* scratch = nullptr;
     {
         std::lock_guard<std::mutex> lk(h->mu);
@@ -615,9 +642,12 @@ int sigma_impl(me_handle* h, const double* momenta, int64_t n_evt, double* out_m
         sel.hel_me = reinterpret_cast<double*>(static_cast<char*>(scratch) + (size_t)chunk * h->bytes_per_event);
         sel.w = sel.hel_me + (size_t)chunk * h->n_good;
     }
+    double* sde = chan ? reinterpret_cast<double*>(static_cast<char*>(scratch) +
+                                                   (size_t)chunk * (h->bytes_per_event + sel_bytes))
+                       : nullptr;
     return run_chunks(h, h->precision, h->d_hel_good, h->n_good, h->hel_per_group, h->groups, chunk,
                       h->jamp_bytes_per_event, momenta, n_evt, out_me2, out_hel, scratch, st, h->profiling,
-                      sel_in ? &sel : nullptr, alphas);
+                      sel_in ? &sel : nullptr, alphas, chan, sde);
 }
 
 }  // namespace
@@ -641,6 +671,21 @@ int me_sigma_alphas(me_handle* h, const double* momenta, int64_t n_evt, const do
 {
     if (n_evt > 0 && !alpha_s_evt) return fail(ME_EINVAL, "alpha_s_evt must be given");
     return sigma_impl(h, momenta, n_evt, out_me2, nullptr, nullptr, stream, alpha_s_evt);
+}
+
+int me_sigma_channel(me_handle* h, const double* momenta, int64_t n_evt, const int* channel, double* out_me2,
+                     void* stream)
+{
+    if (n_evt > 0 && !channel) return fail(ME_EINVAL, "channel ids must be given");
+    return sigma_impl(h, momenta, n_evt, out_me2, nullptr, nullptr, stream, nullptr, channel);
+}
+
+int me_diagrams(const me_handle* h, int* out)
+{
+    if (!h || !out) return fail(ME_EINVAL, "NULL argument");
+    if (!h->P->sde_supported) return fail(ME_EINVAL, "no single-diagram channel weights for this process");
+    std::memcpy(out, h->P->diagram_lines, sizeof(int) * h->P->n_diagrams * h->P->lines_per_diagram);
+    return h->P->n_diagrams;
 }
 
 int me_colour_flows(const me_handle* h, int* out)

@@ -5,10 +5,14 @@
 
 namespace me {
 
+// chan == nullptr: plain kernels; otherwise chan[n_evt] channel ids and sde[n_good][2][ld] the
+// per-lane single-diagram sums (channel, all)
 typedef hipError_t (*amp_launch_f64)(const double* mom, int64_t n_evt, int64_t ld, const signed char* hel,
-                                     int n_good, double mt, double g, double* jamp, hipStream_t st);
+                                     int n_good, double mt, double g, double* jamp, const int* chan, double* sde,
+                                     hipStream_t st);
 typedef hipError_t (*amp_launch_f32)(const double* mom, int64_t n_evt, int64_t ld, const signed char* hel,
-                                     int n_good, double mt, double g, float* jamp, hipStream_t st);
+                                     int n_good, double mt, double g, float* jamp, const int* chan, double* sde,
+                                     hipStream_t st);
 
 struct ProcessDesc {
     const char* name;
@@ -28,6 +32,9 @@ struct ProcessDesc {
     double flops_lane;         // algorithmic flops of the amplitude kernel per (event, helicity)
     double flops_exec_lane;    // flops it executes (more when segments recompute currents)
     int nslot;                 // partial jamp slots per (event, helicity); 0: jamps written directly
+    const int* diagram_lines;  // n_diagrams x lines_per_diagram internal-line masks (0-padded)
+    int lines_per_diagram;
+    int sde_supported;         // single-diagram channel weights available
     amp_launch_f64 launch_f64;
     amp_launch_f32 launch_f32;
 };

@@ -67,6 +67,8 @@ class Process:
             self.cnum, self.cden = [[1]], 1
             self.n_diagrams = 1
             self.n_amplitudes = 1
+            # the one photon diagram: internal line {e+, e-} | {mu+, mu-}
+            self.fd_index, self.kweight, self.lines = [0], [1.0], [(0b1100,)]
             return
         if self.kind == "qline":
             self.diagrams = D.quark_line_diagrams(self.ng)
@@ -85,6 +87,65 @@ class Process:
         self.n_amplitudes = len(self.diagrams)
         self.jcoef = [D.diagram_colour(d, dkind) for d in self.diagrams]
         self.plan = D.Plan(self.diagrams, dkind)
+        self._single_diagram_data(C)
+
+    def _single_diagram_data(self, C):
+        """per amplitude entry: its Feynman diagram (four-gluon colour structures of one
+        diagram share it) and its colour weight K = c^dagger C c, the entry's colour-summed
+        square per |amplitude|^2 (c: its coefficients on the colour flows); per Feynman
+        diagram: its internal lines (bit i = particle i, the side without particle 0).
+        Only the quark-line processes carry single-diagram weights."""
+        self.fd_index, self.kweight, self.lines = None, None, None
+        if self.dkind != "qline":
+            return
+        pidx = {tuple(p): i for i, p in enumerate(self.perms)}
+
+        def strip(t):
+            if t[0] == "L":
+                return t
+            if t[0] == "V3":
+                return ("V3",) + tuple(strip(c) for c in t[1:])
+            return ("V4",) + tuple(strip(c) for c in t[2:])
+
+        keys, self.fd_index, self.kweight = {}, [], []
+        full = (1 << self.npar) - 1
+
+        def canon(m):
+            return full ^ m if m & 1 else m
+
+        def gmask(t):
+            return sum(1 << self.gpar[i] for i in D.leaves(t))
+
+        self.lines = []
+        for d, coef in zip(self.diagrams, self.jcoef):
+            k = tuple(strip(t) for t in d)
+            if k not in keys:
+                keys[k] = len(keys)
+                lines = []
+
+                def walk(t):
+                    if t[0] == "L":
+                        return
+                    lines.append(canon(gmask(t)))
+                    for c in D.children(t):
+                        walk(c)
+
+                for t in d:
+                    walk(t)
+                acc = 1 << 2           # quark propagators: the top plus the blocks before them
+                for t in d[:-1]:
+                    acc |= gmask(t)
+                    lines.append(canon(acc))
+                self.lines.append(tuple(sorted(lines)))
+            self.fd_index.append(keys[k])
+            v = [(pidx[tuple(q)], c) for q, c in coef.items()]
+            K = 0
+            for a, ca in v:
+                for b, cb in v:
+                    # Re(conj(ca) C_ab cb); C is real symmetric, so the sum is real
+                    K += C[a][b] * (ca.re * cb.re + ca.im * cb.im)
+            self.kweight.append(float(K))
+        assert len(keys) == self.n_diagrams
 
     @property
     def nc(self):
@@ -222,6 +283,8 @@ class Process:
                 else:
                     out.append(f"    a = amp_vvvv<R, {t[1]}>({wx}, {ws[0]}, {ws[1]}, {ws[2]}, gs);")
                     flops[0] += FLOPS["amp_vvvv"]
+            if self.fd_index is not None:
+                out.append(f"    SDEACC({self.fd_index[di]}, {self.kweight[di]!r});")
             if steps is None:
                 for seq, c in sorted(self.jcoef[di].items()):
                     out.append(self._jamp_update(self.perm_index[seq], c))
@@ -261,6 +324,7 @@ class Process:
         out.append("    const W4<R> w3 = ext_ubar<R>(PM(3), 0.0, lam[3]);")
         out.append("    const W4<R> w4 = jf<R>(w0, w1, PM(0) + PM(1), gs);")
         out.append("    a = amp_ffv<R>(w3, w2, w4, gs);")
+        out.append("    SDEACC(0, 1.0);")
         out.append("    JADD(0, 0, a.r); JADD(0, 1, a.i);")
         return 4 * FLOPS["ext_spinor"] + FLOPS["p4add"] + FLOPS["jf"] + FLOPS["amp_ffv"] + FLOPS["jamp"]
 
@@ -340,21 +404,25 @@ class Process:
                      '#include "../helas.hpp"', "namespace me {", f"namespace proc_{nm} {{",
                      f"constexpr int NPAR = {self.npar};", f"constexpr int NC = {nc};",
                      f"constexpr int NSLOT = {self.nslot};"]
-                F += self._kernel_text(kname, body, nwin, mode, jamps_in_lds, jamp_mode)
+                F += self._kernel_text(kname, body, nwin, mode, jamps_in_lds, jamp_mode, first=(kname == "amp_seg0"))
                 for R, tag in (("double", "f64"), ("float", "f32")):
                     F.append(f"hipError_t {kname}_launch_{tag}(const double* mom, int64_t n_evt, int64_t ld, "
-                             f"const signed char* hel, int n_good, double mt, double gs, {R}* jamp, hipStream_t st, "
-                             "int64_t blocks)")
+                             f"const signed char* hel, int n_good, double mt, double gs, {R}* jamp, const int* chan, "
+                             "double* sde, hipStream_t st, int64_t blocks)")
                     F.append("{")
-                    F.append(f"    hipLaunchKernelGGL({kname}<{R}>, dim3((unsigned)blocks), dim3(64), 0, st, mom, n_evt, "
-                             "ld, hel, n_good, mt, gs, jamp);")
+                    F.append("    if (chan)")
+                    F.append(f"        hipLaunchKernelGGL(({kname}<{R}, true>), dim3((unsigned)blocks), dim3(64), 0, st, mom, "
+                             "n_evt, ld, hel, n_good, mt, gs, jamp, chan, sde);")
+                    F.append("    else")
+                    F.append(f"        hipLaunchKernelGGL(({kname}<{R}, false>), dim3((unsigned)blocks), dim3(64), 0, st, mom, "
+                             "n_evt, ld, hel, n_good, mt, gs, jamp, nullptr, nullptr);")
                     F.append("    return hipGetLastError();")
                     F.append("}")
                 F += ["}  // namespace", "}  // namespace me"]
                 self.extra_files[f"proc_{nm}_{kname}.hip"] = "\n".join(F) + "\n"
                 for R, tag in (("double", "f64"), ("float", "f32")):
                     L.append(f"hipError_t {kname}_launch_{tag}(const double*, int64_t, int64_t, const signed char*, "
-                             f"int, double, double, {R}*, hipStream_t, int64_t);")
+                             f"int, double, double, {R}*, const int*, double*, hipStream_t, int64_t);")
         else:
             for kname, body, nwin, mode in kernels:
                 L += self._kernel_text(kname, body, nwin, mode, jamps_in_lds, jamp_mode)
@@ -362,11 +430,17 @@ class Process:
         L.append(f"static const int colour_num[NC * NC] = {{{cn}}};")
         L.append(f"static const int final_massive[NPAR - 2] = {{{masses}}};")
         L.append(f"static const int orderings[] = {{{perm_flat}}};")
+        nlines = max(1, self.npar - 3)
+        if self.lines is not None:
+            flat = ", ".join(str(x) for ln in self.lines for x in (list(ln) + [0] * (nlines - len(ln))))
+        else:
+            flat = "0"
+        L.append(f"static const int diagram_lines[] = {{{flat}}};")
         if self.segments:
             L += self._reduce_text()
         L.append("template <class R>")
         L.append("static hipError_t launch(const double* mom, int64_t n_evt, int64_t ld, const signed char* hel, "
-                 "int n_good, double mt, double gs, R* jamp, hipStream_t st)")
+                 "int n_good, double mt, double gs, R* jamp, const int* chan, double* sde, hipStream_t st)")
         L.append("{")
         L.append("    int64_t blocks = ((n_evt + 63) / 64) * n_good;")
         L.append("    if (blocks == 0) return hipSuccess;")
@@ -374,14 +448,18 @@ class Process:
             if self.segments:
                 L.append("    {")
                 L.append(f"        hipError_t e = sizeof(R) == 8 ? {kname}_launch_f64(mom, n_evt, ld, hel, n_good, mt, gs, "
-                         "(double*)jamp, st, blocks)")
+                         "(double*)jamp, chan, sde, st, blocks)")
                 L.append(f"                                      : {kname}_launch_f32(mom, n_evt, ld, hel, n_good, mt, gs, "
-                         "(float*)jamp, st, blocks);")
+                         "(float*)jamp, chan, sde, st, blocks);")
                 L.append("        if (e != hipSuccess) return e;")
                 L.append("    }")
             else:
-                L.append(f"    hipLaunchKernelGGL({kname}<R>, dim3((unsigned)blocks), dim3(64), 0, st, mom, n_evt, ld, hel, "
-                         "n_good, mt, gs, jamp);")
+                L.append("    if (chan)")
+                L.append(f"        hipLaunchKernelGGL(({kname}<R, true>), dim3((unsigned)blocks), dim3(64), 0, st, mom, n_evt, "
+                         "ld, hel, n_good, mt, gs, jamp, chan, sde);")
+                L.append("    else")
+                L.append(f"        hipLaunchKernelGGL(({kname}<R, false>), dim3((unsigned)blocks), dim3(64), 0, st, mom, n_evt, "
+                         "ld, hel, n_good, mt, gs, jamp, nullptr, nullptr);")
         if self.segments:
             L.append("    hipLaunchKernelGGL(reduce_kernel<R>, dim3((unsigned)((n_evt + 255) / 256), (unsigned)n_good), "
                      "dim3(256), 0, st, jamp, ld, n_good, n_evt);")
@@ -396,6 +474,7 @@ class Process:
         L.append(f"        proc_{nm}::colour_num, {self.cden}, proc_{nm}::final_massive, proc_{nm}::orderings, "
                  f"{n_order},")
         L.append(f"        {self.n_diagrams}, {self.n_amplitudes}, {fl}.0, {self.flops_exec}.0, proc_{nm}::NSLOT,")
+        L.append(f"        proc_{nm}::diagram_lines, {nlines}, {0 if self.lines is None else 1},")
         L.append(f"        proc_{nm}::launch<double>, proc_{nm}::launch<float>,")
         L.append("    };")
         L.append("    return &d;")
@@ -403,16 +482,20 @@ class Process:
         L.append("}  // namespace me")
         return "\n".join(L) + "\n"
 
-    def _kernel_text(self, kname, body, nwin, mode, jamps_in_lds, jamp_mode):
+    def _kernel_text(self, kname, body, nwin, mode, jamps_in_lds, jamp_mode, first=True):
         """one amplitude kernel: momenta staging, helicity signs, jamp storage, body, output.
         mode 'jamps': the NC jamps are written at the end, layout [h][2c + re/im][column];
         mode 'slots': the body flushes window slots to partial slots (JFLUSH), layout
-        [h][2s + re/im][column] after the jamp region."""
+        [h][2s + re/im][column] after the jamp region.
+        With SDE the kernel also sums, per lane, the colour-summed single-diagram squares
+        K_e |a_e|^2 of its amplitude entries (all, and those of the event's channel chan[e])
+        into sde[h][0/1][column]; `first` is false for segment kernels that add to the
+        sums of the segments before them."""
         L = []
-        L.append("template <class R>")
+        L.append("template <class R, bool SDE>")
         L.append(f"__global__ __launch_bounds__(64) void {kname}(const double* __restrict__ mom, int64_t n_evt, "
                  "int64_t ld, const signed char* __restrict__ hel, int n_good, double mt, double gs, "
-                 "R* __restrict__ jamp)")
+                 "R* __restrict__ jamp, const int* __restrict__ chan, double* __restrict__ sde)")
         L.append("{")
         L.append("    __shared__ double lds[4 * NPAR * 64];")
         L.append("    const int lane = threadIdx.x;")
@@ -460,7 +543,24 @@ class Process:
             L.append("#define JFLUSH(s, p) do { po[(int64_t)(2 * (p)) * ld] = JGET(s, 0); "
                      "po[(int64_t)(2 * (p) + 1) * ld] = JGET(s, 1); JZERO(s, 0); JZERO(s, 1); } while (0)")
         L.append("    cx<R> a;")
+        L.append("    int ch = -1;")
+        L.append("    double sde_ch = 0.0, sde_all = 0.0;")
+        L.append("    if constexpr (SDE) ch = (e < n_evt) ? chan[e] : -1;")
+        L.append("#define SDEACC(d, k) do { if constexpr (SDE) { "
+                 "const double w_ = (k) * ((double)a.r * (double)a.r + (double)a.i * (double)a.i); "
+                 "sde_all += w_; sde_ch += ((d) == ch) ? w_ : 0.0; } } while (0)")
         L.extend(body)
+        L.append("    if constexpr (SDE) {")
+        L.append("        if (e < n_evt) {")
+        L.append("            double* so = sde + (int64_t)h * 2 * ld + e;")
+        if first:
+            L.append("            so[0] = sde_ch;")
+            L.append("            so[ld] = sde_all;")
+        else:
+            L.append("            so[0] += sde_ch;")
+            L.append("            so[ld] += sde_all;")
+        L.append("        }")
+        L.append("    }")
         if mode == "jamps":
             L.append("    if (e < n_evt) {")
             L.append("        R* o = jamp + (int64_t)h * (2 * NC) * ld + e;")
@@ -470,7 +570,7 @@ class Process:
             L.append("            o[(2 * s + 1) * ld] = JGET(s, 1);")
             L.append("        }")
             L.append("    }")
-        for m in ("PM", "JADD", "JGET", "JZERO", "JFLUSH"):
+        for m in ("PM", "JADD", "JGET", "JZERO", "JFLUSH", "SDEACC"):
             L.append(f"#undef {m}")
         L.append("}")
         return L

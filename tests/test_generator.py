@@ -186,3 +186,22 @@ def test_window_program_reproduces_direct_accumulation():
     for s, j in enumerate(P.partial_jamp):
         red[j] += partial[s]
     assert np.allclose(red, direct, atol=1e-12 * np.abs(direct).max())
+
+
+@pytest.mark.parametrize("name", ["gg_tt", "gg_ttg", "gg_ttgg"])
+def test_single_diagram_data_matches_oracle(name):
+    """per Feynman diagram (matched by internal lines) the generator's colour weights
+    K = c^dagger C c of its entries equal the oracle's numeric colour sums"""
+    import collections
+    from oracle import diagrams as Dg
+    P = emit.Process(name)
+    P.source()
+    g = collections.defaultdict(list)
+    for fd, k in zip(P.fd_index, P.kweight):
+        g[P.lines[fd]].append(round(k, 9))
+    o = collections.defaultdict(list)
+    for (d, s), k in zip(Dg.entries(name), Dg.colour_weights_K(name)):
+        o[Dg.descriptor(name, d)].append(round(k, 9))
+    assert set(g) == set(o) and len(g) == P.n_diagrams
+    for key in g:
+        assert sorted(g[key]) == sorted(o[key])

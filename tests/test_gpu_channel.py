@@ -1,0 +1,88 @@
+"""GPU single-diagram channel weights (me_sigma_channel) against the oracle's own Feynman
+diagrams (oracle/diagrams.py: enumeration, Lorentz parts and colour factors of its own).
+Diagrams are matched by their internal lines, so the two numberings need not agree."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import diagrams as Dg
+from tests import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def make_process(name, precision="fp64"):
+    from paper_2210_11122_amd import Process
+    return Process(name, m_top=W.M_TOP, alpha_em=W.ALPHA_EM, alpha_s=W.ALPHA_S, precision=precision)
+
+
+@pytest.mark.parametrize("name,n_evt,n_chan", [("gg_tt", 4, 3), ("gg_ttg", 3, 16), ("gg_ttgg", 2, 12)])
+def test_channel_weights_match_oracle(name, n_evt, n_chan):
+    print(f"case channel weights {name}", flush=True)
+    proc = make_process(name)
+    lines = proc.diagrams()
+    assert len(lines) == proc.info["n_diagrams"]
+    ng = oracle.n_par(name) - 2
+    assert set(lines) == {Dg.descriptor(name, d) for d in Dg.diagrams(ng)}
+    p = oracle.rambo(41, W.sqrt_s(name), W.final_masses(name), n_evt)
+    chans = np.linspace(0, len(lines) - 1, n_chan).astype(np.int32)
+    x = torch.from_numpy(np.repeat(p, len(chans), axis=0)).cuda()
+    ch = torch.from_numpy(np.tile(chans, n_evt)).cuda()
+    got = proc.sigma_channel(x, ch).cpu().numpy().reshape(n_evt, len(chans))
+    me = proc.sigma(torch.from_numpy(p).cuda()).cpu().numpy()
+    K = Dg.colour_weights_K(name)
+    for e in range(n_evt):
+        Wd = Dg.diagram_weights(name, p[e], W.PARAMS, K)
+        tot = sum(Wd.values())
+        for k, c in enumerate(chans):
+            want = me[e] * Wd[lines[c]] / tot
+            assert got[e, k] == pytest.approx(want, rel=1e-12), (e, int(c))
+
+
+def test_channel_weights_sum_to_one_and_no_channel():
+    name = "gg_ttgg"
+    proc = make_process(name)
+    nd = proc.info["n_diagrams"]
+    p = oracle.rambo(42, W.sqrt_s(name), W.final_masses(name), 3)
+    x = torch.from_numpy(np.repeat(p, nd, axis=0)).cuda()
+    ch = torch.from_numpy(np.tile(np.arange(nd, dtype=np.int32), 3)).cuda()
+    got = proc.sigma_channel(x, ch).cpu().numpy().reshape(3, nd)
+    me = proc.sigma(torch.from_numpy(p).cuda()).cpu().numpy()
+    assert np.all(got >= 0)
+    assert np.allclose(got.sum(axis=1), me, rtol=1e-12)
+    none = proc.sigma_channel(torch.from_numpy(p).cuda(), torch.full((3,), -1, dtype=torch.int32).cuda())
+    assert np.array_equal(none.cpu().numpy(), me)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_fp16"])
+def test_channel_weights_ttggg(precision):
+    """gg_ttggg (segment kernels add their sums in turn): the weights of all 1240 channels
+    of an event sum to one"""
+    print(f"case channel weights gg_ttggg {precision}", flush=True)
+    name = "gg_ttggg"
+    proc = make_process(name, precision)
+    nd = proc.info["n_diagrams"]
+    assert nd == 1240
+    p = oracle.rambo(43, W.sqrt_s(name), W.final_masses(name), 2)
+    x = torch.from_numpy(np.repeat(p, nd, axis=0)).cuda()
+    ch = torch.from_numpy(np.tile(np.arange(nd, dtype=np.int32), 2)).cuda()
+    got = proc.sigma_channel(x, ch).cpu().numpy().reshape(2, nd)
+    me = proc.sigma(torch.from_numpy(p).cuda()).cpu().numpy()
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    assert np.all(got >= 0) and np.allclose(got.sum(axis=1), me, rtol=tol)
+
+
+def test_channel_rejects():
+    import ctypes
+    from paper_2210_11122_amd import binding
+    L = binding.load()
+    gg = make_process("gg_gg")
+    x = torch.zeros((4, 4, 4), dtype=torch.float64, device="cuda")
+    out = torch.empty(4, dtype=torch.float64, device="cuda")
+    ch = torch.zeros(4, dtype=torch.int32, device="cuda")
+    v = lambda t: ctypes.c_void_p(t.data_ptr())
+    assert L.me_sigma_channel(gg._h, v(x), 4, v(ch), v(out), None) == -1
+    tt = make_process("gg_tt")
+    host = np.zeros(4, dtype=np.int32)
+    assert L.me_sigma_channel(tt._h, v(x), 4, ctypes.c_void_p(host.ctypes.data), v(out), None) == -1

@@ -13,6 +13,8 @@
  *   gg_tt    (g, g, t, t~)          gg_ttg  (g, g, t, t~, g)
  *   gg_ttgg  (g, g, t, t~, g, g)    gg_ttggg (g, g, t, t~, g, g, g)
  *   gg_gg    (g, g, g, g)           (test process)
+ *   ee_mumu_z (e+, e-, mu+, mu-)     photon and Z exchange (M_Z = 91.188, Gamma_Z = 2.441404,
+ *                                    M_W = 80.419 GeV, sin^2 theta_W = 1 - M_W^2/M_Z^2)
  * The returned value is the spin- and colour-averaged |M|^2 WITHOUT the identical-
  * particle factor (me_info reports that factor as sym_factor).
  *
@@ -92,7 +94,7 @@ int me_sigma_select(me_handle *h, const double *momenta, int64_t n_evt, const do
  * alpha_s_evt = DEVICE double[n_evt], alpha_s at each event's renormalisation scale, chosen and
  * evaluated by the caller.  Exact for these tree-level QCD processes: |M|^2 is homogeneous of
  * degree n_par - 2 in alpha_s, so the library evaluates the amplitudes at the handle's alpha_s
- * and multiplies by (alpha_s_evt[e] / alpha_s)^(n_par - 2).  No effect for ee_mumu (QED).
+ * and multiplies by (alpha_s_evt[e] / alpha_s)^(n_par - 2).  No effect for ee_mumu and ee_mumu_z.
  * ME_EINVAL for NULL or host pointers. */
 int me_sigma_alphas(me_handle *h, const double *momenta, int64_t n_evt, const double *alpha_s_evt,
                     double *out_me2, void *stream);

@@ -12,6 +12,7 @@ Process ids and particle orders:
   gg_ttgg  (g, g, t, t~, g, g)
   gg_ttggg (g, g, t, t~, g, g, g)
   gg_gg    (g, g, g, g)                       test process (pure gluon vertices)
+  ee_mumu_z (e+, e-, mu+, mu-)                photon and Z exchange
 Parameters: params = (m_t, alpha_em, alpha_s).
 """
 import ctypes
@@ -21,7 +22,7 @@ from concurrent.futures import ThreadPoolExecutor
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-PROCESSES = {"ee_mumu": 0, "gg_tt": 1, "gg_ttg": 2, "gg_ttgg": 3, "gg_ttggg": 4, "gg_gg": 5}
+PROCESSES = {"ee_mumu": 0, "gg_tt": 1, "gg_ttg": 2, "gg_ttgg": 3, "gg_ttggg": 4, "gg_gg": 5, "ee_mumu_z": 6}
 DEFAULT_PARAMS = (173.0, 1.0 / 132.507, 0.118)
 
 _D = ctypes.POINTER(ctypes.c_double)
@@ -47,6 +48,7 @@ def _load(name):
     lib.or_colour_matrix_methods.argtypes = [ctypes.c_int, _D, _D]
     lib.or_amp_explicit_colour.argtypes = [ctypes.c_int, _D, _D, ctypes.c_int, _I, _D, _D]
     lib.or_tree_amp.argtypes = [ctypes.c_int, _D, _D, ctypes.c_int, _I, ctypes.c_int, _D]
+    lib.or_ee_z_amp.argtypes = [_D, _D, ctypes.c_int, ctypes.c_int, _D]
     lib.or_me_brute_colour.restype = ctypes.c_double
     lib.or_me_brute_colour.argtypes = [ctypes.c_int, _D, _D]
     lib.or_spin_sums.argtypes = [_D, ctypes.c_double, ctypes.c_int, _D, _D, _D]
@@ -249,3 +251,32 @@ def draw(weights, r):
         if target < cum:
             return j
     return last
+
+
+def ee_z_amplitude(p, h, diagrams=3, params=None):
+    """ee -> mumu with Z: amplitude of helicity h from the photon (1), the Z (2) or both (3)"""
+    out = np.zeros(2)
+    lib().or_ee_z_amp(_ptr(_params(params)), _ptr(np.ascontiguousarray(p, dtype=np.float64)), h, diagrams,
+                      _ptr(out))
+    return out[0] + 1j * out[1]
+
+
+_GOOD = {}
+
+
+def good_helicities(process, sqrt_s, final_masses, params=None, n_events=1024, seed=0x5EED, threshold=1e-20):
+    """helicity combinations kept by the helicity filter, computed by the oracle itself: h is
+    kept iff max over n_events RAMBO events (stream `seed`) of |M_h|^2 / sum_h |M_h|^2 exceeds
+    the threshold"""
+    key = (process, sqrt_s, tuple(final_masses), None if params is None else tuple(params), n_events, seed,
+           threshold)
+    if key not in _GOOD:
+        p = rambo(seed, sqrt_s, final_masses, n_events)
+        r = np.zeros(1 << n_par(process))
+        for ev in p:
+            _, hel = me(process, ev, params=params, per_helicity=True)
+            tot = hel.sum()
+            if tot > 0:
+                r = np.maximum(r, hel / tot)
+        _GOOD[key] = [h for h in range(len(r)) if r[h] > threshold]
+    return _GOOD[key]

@@ -6,7 +6,8 @@ the features of its ME engine: the integrand of channel c is |M|^2 times the cha
 W_c / sum_d W_d, with W_d a single diagram's squared amplitude.  This module computes W_d
 for the quark-line processes gg -> t t~ + gluons from the definition:
 
-  W_d = sum over helicities, over the diagram's four-gluon colour structures s (taken
+  W_d = sum over the helicities the filter keeps (see ``good_helicities``), over the
+        diagram's four-gluon colour structures s (taken
         incoherently), of sum over explicit colours |CF_ds(colours) L_ds(helicity)|^2
       = sum_h sum_s |L_ds(h)|^2 K_ds,  K_ds = sum_colours |CF_ds|^2,
 
@@ -255,22 +256,24 @@ def colour_weights_K(process):
     return np.array([np.sum(np.abs(colour_tensor(d, s, ng)) ** 2) for d, s in entries(process)])
 
 
-def diagram_weights(process, p, params=None, K=None):
-    """{descriptor: W_d} for one event (all helicities)"""
+def diagram_weights(process, p, params=None, K=None, helicities=None):
+    """{descriptor: W_d} for one event, summed over `helicities` (default: all).  A
+    helicity whose full amplitude vanishes can still have non-zero single diagrams, so the
+    set matters: MadEvent sums over the helicities its filter keeps."""
     ents = entries(process)
     K = colour_weights_K(process) if K is None else K
-    nh = 1 << n_par(process)
+    hs = range(1 << n_par(process)) if helicities is None else helicities
     W = {}
     for (d, s), k in zip(ents, K):
         w = 0.0
-        for h in range(nh):
+        for h in hs:
             w += abs(lorentz(process, p, h, d, s, params)) ** 2
         key = descriptor(process, d)
         W[key] = W.get(key, 0.0) + w * k
     return W
 
 
-def channel_factor(process, p, channel_descriptor, params=None, K=None):
+def channel_factor(process, p, channel_descriptor, params=None, K=None, helicities=None):
     """W_c / sum_d W_d for the diagram with the given internal lines"""
-    W = diagram_weights(process, p, params, K)
+    W = diagram_weights(process, p, params, K, helicities)
     return W[channel_descriptor] / sum(W.values())

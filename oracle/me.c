@@ -52,8 +52,15 @@ typedef OR_REAL _Complex cplx;
 #define NPERM_MAX 120
 
 enum { P_EE_MUMU = 0, P_GG_TT = 1, P_GG_TTG = 2, P_GG_TTGG = 3, P_GG_TTGGG = 4, P_GG_GG = 5,
-       N_PROC = 6 };
-static const int N_PAR[N_PROC] = {4, 4, 5, 6, 7, 4};
+       P_EE_MUMU_Z = 6, N_PROC = 7 };
+static const int N_PAR[N_PROC] = {4, 4, 5, 6, 7, 4, 4};
+static int is_qcd(int proc) { return proc >= P_GG_TT && proc <= P_GG_GG; }
+static int is_ee(int proc) { return proc == P_EE_MUMU || proc == P_EE_MUMU_Z; }
+/* electroweak constants of ee -> mumu with Z exchange: M_Z, Gamma_Z [GeV], M_W [GeV]
+ * (sin^2 theta_W = 1 - M_W^2 / M_Z^2) */
+#define EW_MZ ((real)91.188L)
+#define EW_WZ ((real)2.441404L)
+#define EW_MW ((real)80.419L)
 
 /* ------------------------------------------------------------------------------------ */
 /* constant tables: Dirac matrices, SU(3) generators, structure constants                */
@@ -653,6 +660,53 @@ static cplx amp_eemumu(const double *p, const real *par, int h, int basis)
     return (I * e) * (I * e) * (-I / s) * dot_cc(Je, Jm);
 }
 
+/* e+ e- -> mu+ mu- with photon and Z exchange (Peskin & Schroeder's electroweak vertices):
+ * photon -i e Q gamma^mu, Z -i (g / cos theta_W) gamma^mu (T3 P_L - Q sin^2 theta_W) with
+ * P_L = (1 - gamma5)/2, g = e / sin theta_W; propagators -i g_{mu nu} / s and
+ * -i g_{mu nu} / (s - M_Z^2 + i M_Z Gamma_Z) (the k_mu k_nu term vanishes between massless
+ * currents).  For e and mu: Q = -1, T3 = -1/2.  gamma5 is diag(-1, -1, 1, 1) in this
+ * representation. */
+static cplx amp_eemumu_z(const double *p, const real *par, int h, int diagram_mask)
+{
+    real e = sqrt(4 * PI_R * par[1]);
+    real sw2 = 1 - EW_MW * EW_MW / (EW_MZ * EW_MZ), cw2 = 1 - sw2;
+    real gz = e / sqrt(sw2 * cw2);
+    real cl = -0.5 + sw2, cr = sw2;              /* T3 - Q sw2 on P_L; -Q sw2 on P_R */
+    real p1[4], p2[4], p3[4], p4[4];
+    for (int mu = 0; mu < 4; ++mu) {
+        p1[mu] = p[mu]; p2[mu] = p[4 + mu]; p3[mu] = p[8 + mu]; p4[mu] = p[12 + mu];
+    }
+    cplx v1[4], v1bar[4], u2[4], v3[4], u4[4], u4bar[4];
+    spinor_v(p1, 0, helicity_of(4, h, 0), v1);
+    dirac_bar(v1, v1bar);
+    spinor_u(p2, 0, helicity_of(4, h, 1), u2);
+    spinor_v(p3, 0, helicity_of(4, h, 2), v3);
+    spinor_u(p4, 0, helicity_of(4, h, 3), u4);
+    dirac_bar(u4, u4bar);
+    /* chiral projections of the column spinors: P_L keeps components 0, 1 */
+    cplx u2L[4] = {u2[0], u2[1], 0, 0}, u2R[4] = {0, 0, u2[2], u2[3]};
+    cplx v3L[4] = {v3[0], v3[1], 0, 0}, v3R[4] = {0, 0, v3[2], v3[3]};
+    cplx Je[4], Jm[4], JeL[4], JeR[4], JmL[4], JmR[4], JeZ[4], JmZ[4];
+    current(v1bar, u2, Je);
+    current(u4bar, v3, Jm);
+    current(v1bar, u2L, JeL);
+    current(v1bar, u2R, JeR);
+    current(u4bar, v3L, JmL);
+    current(u4bar, v3R, JmR);
+    for (int mu = 0; mu < 4; ++mu) {
+        JeZ[mu] = cl * JeL[mu] + cr * JeR[mu];
+        JmZ[mu] = cl * JmL[mu] + cr * JmR[mu];
+    }
+    real P[4];
+    for (int mu = 0; mu < 4; ++mu) P[mu] = p1[mu] + p2[mu];
+    real s = dot_rr(P, P);
+    cplx a = 0;
+    if (diagram_mask & 1) a += (-I * e * -1) * (-I * e * -1) * (-I / s) * dot_cc(Je, Jm);
+    if (diagram_mask & 2)
+        a += (-I * gz) * (-I * gz) * (-I / (s - EW_MZ * EW_MZ + I * EW_MZ * EW_WZ)) * dot_cc(JeZ, JmZ);
+    return a;
+}
+
 /* ------------------------------------------------------------------------------------ */
 /* colour-ordered amplitudes and the colour-summed |M_h|^2                               */
 
@@ -685,6 +739,10 @@ static real me_helicity(int proc, const double *p, const real *par, int h, int b
 {
     if (proc == P_EE_MUMU) {
         cplx a = amp_eemumu(p, par, h, basis);
+        return creal(a * conj(a));
+    }
+    if (proc == P_EE_MUMU_Z) {
+        cplx a = amp_eemumu_z(p, par, h, 3);
         return creal(a * conj(a));
     }
     cplx A[NPERM_MAX];
@@ -845,7 +903,7 @@ int or_n_par(int proc) { return (proc >= 0 && proc < N_PROC) ? N_PAR[proc] : -1;
 int or_n_colour_orderings(int proc)
 {
     if (proc < 0 || proc >= N_PROC) return -1;
-    if (proc == P_EE_MUMU) return 1;
+    if (is_ee(proc)) return 1;
     return factorial(proc == P_GG_GG ? 3 : n_gluons(proc));
 }
 int or_real_bytes(void) { return (int)sizeof(real); }
@@ -857,6 +915,19 @@ static void load_par(const double *params, real par[3])
 
 /* averaged sum over all helicities and colours; params = {m_t, alpha_em, alpha_s};
  * me_hel (optional) receives the colour-summed |M_h|^2 of every helicity */
+/* ee -> mumu with Z: the amplitude of helicity h from the diagrams in `mask` (1 photon,
+ * 2 Z, 3 both) */
+int or_ee_z_amp(const double *params, const double *p, int h, int mask, double *out)
+{
+    tables();
+    real par[3];
+    load_par(params, par);
+    cplx a = amp_eemumu_z(p, par, h, mask);
+    out[0] = (double)creal(a);
+    out[1] = (double)cimag(a);
+    return 0;
+}
+
 double or_me(int proc, const double *params, const double *p, int basis, double *me_hel)
 {
     if (proc < 0 || proc >= N_PROC) return -1;
@@ -871,7 +942,7 @@ double or_me(int proc, const double *params, const double *p, int basis, double 
         if (me_hel) me_hel[h] = (double)x;
         sum += x;
     }
-    real avg = (proc == P_EE_MUMU) ? 4 : 256;
+    real avg = is_ee(proc) ? 4 : 256;
     return (double)(sum / avg);
 }
 
@@ -890,7 +961,7 @@ int or_me_batch(int proc, const double *params, const double *p, int64_t n_evt, 
 int or_partials(int proc, const double *params, const double *p, int h, int basis,
                 int gauge_gluon, double *out)
 {
-    if (proc <= P_EE_MUMU || proc >= N_PROC) return -1;
+    if (!is_qcd(proc)) return -1;
     real par[3];
     load_par(params, par);
     cplx A[NPERM_MAX];
@@ -905,7 +976,7 @@ int or_partials(int proc, const double *params, const double *p, int h, int basi
 /* the permutations that label the colour orderings, lexicographic */
 int or_orderings(int proc, int *out)
 {
-    if (proc <= P_EE_MUMU || proc >= N_PROC) return -1;
+    if (!is_qcd(proc)) return -1;
     int perms[NPERM_MAX][NG_MAX];
     int n = (proc == P_GG_GG) ? 3 : n_gluons(proc);
     int np = perm_list(n, perms);
@@ -916,7 +987,7 @@ int or_orderings(int proc, int *out)
 
 int or_colour_matrix(int proc, double *out)
 {
-    if (proc <= P_EE_MUMU || proc >= N_PROC) return -1;
+    if (!is_qcd(proc)) return -1;
     int kind = (proc == P_GG_GG) ? 1 : 0;
     int n = n_gluons(proc);
     int np = factorial(kind ? n - 1 : n);
@@ -948,7 +1019,7 @@ int or_colour_matrix_methods(int n, double *direct, double *relabel)
 int or_amp_explicit_colour(int proc, const double *params, const double *p, int h,
                            const int *colours, double *dressed, double *decomposed)
 {
-    if (proc <= P_EE_MUMU || proc >= N_PROC) return -1;
+    if (!is_qcd(proc)) return -1;
     tables();
     real par[3];
     load_par(params, par);
@@ -1008,7 +1079,7 @@ int or_amp_explicit_colour(int proc, const double *params, const double *p, int 
 int or_tree_amp(int proc, const double *params, const double *p, int h, const int *prog, int len,
                 double *out)
 {
-    if (proc <= P_EE_MUMU || proc >= P_GG_GG) return -1;
+    if (!is_qcd(proc) || proc == P_GG_GG) return -1;
     tables();
     real par[3];
     load_par(params, par);
@@ -1084,7 +1155,7 @@ int or_tree_amp(int proc, const double *params, const double *p, int h, const in
  * |M|^2 from the colour-dressed recursion (no colour matrix, no decomposition). */
 double or_me_brute_colour(int proc, const double *params, const double *p)
 {
-    if (proc <= P_EE_MUMU || proc >= N_PROC) return -1;
+    if (!is_qcd(proc)) return -1;
     tables();
     real par[3];
     load_par(params, par);

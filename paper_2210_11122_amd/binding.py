@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(PKG, "libme.so")
 ME_FP64, ME_MIXED_FP16, ME_MIXED_BF16 = 0, 1, 2
 PRECISIONS = {"fp64": ME_FP64, "mixed_fp16": ME_MIXED_FP16, "mixed_bf16": ME_MIXED_BF16}
 ME_OK = 0
-PROCESSES = ["ee_mumu", "gg_tt", "gg_ttg", "gg_ttgg", "gg_ttggg", "gg_gg"]
+PROCESSES = ["ee_mumu", "gg_tt", "gg_ttg", "gg_ttgg", "gg_ttggg", "gg_gg", "ee_mumu_z"]
 
 
 class MeError(RuntimeError):

@@ -346,6 +346,36 @@ __device__ __forceinline__ cx<R> amp_ffv(const W4<R>& u, const W4<R>& s, const W
     cx<R> x = u.c[0] * t.c[0] + u.c[1] * t.c[1] + u.c[2] * t.c[2] + u.c[3] * t.c[3];
     return (R)g * mul_i(x);
 }
+// Chiral couplings (gamma5 = diag(-1, -1, 1, 1): P_L keeps components 0, 1 of a column spinor).
+// Massive vector boson emitted by the pair (ubar, psi) through i gz gamma^mu (cl P_L + cr P_R),
+// with the propagator -i g_{mu nu} / (P^2 - M^2 + i M Gamma) (its P_mu P_nu term drops out
+// between massless currents): (gz / (P^2 - M^2 + i M Gamma)) ubar gamma^mu (cl P_L + cr P_R) psi
+template <class R>
+__device__ __forceinline__ W4<R> jf_chiral(const W4<R>& u, const W4<R>& s, const P4& P, double gz, double cl,
+                                           double cr, double M, double Gam)
+{
+    const double dr = msq(P) - M * M, di = M * Gam;
+    const double inv = gz * rcp(dr * dr + di * di);
+    const cx<R> f = {(R)(dr * inv), (R)(-di * inv)};
+    const R L = (R)cl, Rr = (R)cr;
+    cx<R> u0s2 = u.c[0] * s.c[2], u1s3 = u.c[1] * s.c[3], u2s0 = u.c[2] * s.c[0], u3s1 = u.c[3] * s.c[1];
+    cx<R> u0s3 = u.c[0] * s.c[3], u1s2 = u.c[1] * s.c[2], u2s1 = u.c[2] * s.c[1], u3s0 = u.c[3] * s.c[0];
+    W4<R> o;
+    o.c[0] = f * (Rr * (u0s2 + u1s3) + L * (u2s0 + u3s1));
+    o.c[1] = f * (Rr * (u0s3 + u1s2) - L * (u2s1 + u3s0));
+    o.c[2] = f * mul_i(Rr * (u1s2 - u0s3) + L * (u2s1 - u3s0));
+    o.c[3] = f * (Rr * (u0s2 - u1s3) + L * (u3s1 - u2s0));
+    return o;
+}
+// amplitude ubar (i gz gamma.G (cl P_L + cr P_R)) psi
+template <class R>
+__device__ __forceinline__ cx<R> amp_ffv_chiral(const W4<R>& u, const W4<R>& s, const W4<R>& G, double gz,
+                                                double cl, double cr)
+{
+    W4<R> t = gslash_col<R>(G, s);   // t0, t1 come from psi's components 2, 3 (P_R); t2, t3 from 0, 1
+    cx<R> x = (R)cr * (u.c[0] * t.c[0] + u.c[1] * t.c[1]) + (R)cl * (u.c[2] * t.c[2] + u.c[3] * t.c[3]);
+    return (R)gz * mul_i(x);
+}
 // amplitude of a three-gluon vertex with legs (x, a, b), incoming momenta kx, ka, kb:
 // g [(Wx.Wa)((kx-ka).Wb) + (Wa.Wb)((ka-kb).Wx) + (Wb.Wx)((kb-kx).Wa)]
 template <class R>

@@ -33,8 +33,9 @@ int fail(int code, const std::string& msg)
 
 const me::ProcessDesc* find_process(const char* name)
 {
-    const me::ProcessDesc* all[] = {me::process_ee_mumu(), me::process_gg_tt(),   me::process_gg_ttg(),
-                                    me::process_gg_ttgg(), me::process_gg_ttggg(), me::process_gg_gg()};
+    const me::ProcessDesc* all[] = {me::process_ee_mumu(), me::process_gg_tt(),    me::process_gg_ttg(),
+                                    me::process_gg_ttgg(), me::process_gg_ttggg(), me::process_gg_gg(),
+                                    me::process_ee_mumu_z()};
     for (auto* p : all)
         if (p && std::strcmp(p->name, name) == 0) return p;
     return nullptr;

@@ -45,5 +45,6 @@ const ProcessDesc* process_gg_ttg();
 const ProcessDesc* process_gg_ttgg();
 const ProcessDesc* process_gg_ttggg();
 const ProcessDesc* process_gg_gg();
+const ProcessDesc* process_ee_mumu_z();
 
 }  // namespace me

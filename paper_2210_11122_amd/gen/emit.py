@@ -22,19 +22,23 @@ from . import colour, diagrams as D
 # flops per helas.hpp routine (see module docstring)
 FLOPS = {
     "ext_vec": 22, "ext_spinor": 26, "fstr": 141, "jf": 89, "vvv_cur": 151, "vvvv_cur": 134,
+    "jf_chiral": 137, "amp_ffv_chiral": 100,
     "amp_ffv": 96, "amp_vvv": 156, "amp_vvvv": 137, "p4add": 4, "jamp": 2,
 }
 
 QCD_PROCESSES = {"gg_tt": 2, "gg_ttg": 3, "gg_ttgg": 4, "gg_ttggg": 5}
 # name -> (segment kernels, LDS jamp-window slots, weight of window misses in the schedule)
 SEGMENTS = {"gg_ttggg": (8, 24, 1.0)}
-ALL_PROCESSES = ["ee_mumu", "gg_tt", "gg_ttg", "gg_ttgg", "gg_ttggg", "gg_gg"]
+ALL_PROCESSES = ["ee_mumu", "gg_tt", "gg_ttg", "gg_ttgg", "gg_ttggg", "gg_gg", "ee_mumu_z"]
+# electroweak constants of ee -> mumu with Z exchange: M_Z, Gamma_Z, M_W [GeV]
+EW_MZ, EW_WZ, EW_MW = 91.188, 2.441404, 80.419
 
 
 class Process:
     def __init__(self, name):
         self.name = name
-        if name == "ee_mumu":
+        self.zboson = name == "ee_mumu_z"
+        if name in ("ee_mumu", "ee_mumu_z"):
             self.kind, self.npar, self.ng = "ee", 4, 0
             self.gpar = []
             self.final_masses = ["0", "0"]
@@ -65,10 +69,10 @@ class Process:
         if self.kind == "ee":
             self.perms = [()]
             self.cnum, self.cden = [[1]], 1
-            self.n_diagrams = 1
-            self.n_amplitudes = 1
-            # the one photon diagram: internal line {e+, e-} | {mu+, mu-}
-            self.fd_index, self.kweight, self.lines = [0], [1.0], [(0b1100,)]
+            # the photon (and Z) diagram: internal line {e+, e-} | {mu+, mu-}
+            nd = 2 if self.zboson else 1
+            self.n_diagrams = self.n_amplitudes = nd
+            self.fd_index, self.kweight, self.lines = list(range(nd)), [1.0] * nd, [(0b1100,)] * nd
             return
         if self.kind == "qline":
             self.diagrams = D.quark_line_diagrams(self.ng)
@@ -326,7 +330,20 @@ class Process:
         out.append("    a = amp_ffv<R>(w3, w2, w4, gs);")
         out.append("    SDEACC(0, 1.0);")
         out.append("    JADD(0, 0, a.r); JADD(0, 1, a.i);")
-        return 4 * FLOPS["ext_spinor"] + FLOPS["p4add"] + FLOPS["jf"] + FLOPS["amp_ffv"] + FLOPS["jamp"]
+        fl = 4 * FLOPS["ext_spinor"] + FLOPS["p4add"] + FLOPS["jf"] + FLOPS["amp_ffv"] + FLOPS["jamp"]
+        if self.zboson:
+            # Z exchange: i (g / cos theta_W) gamma^mu (T3 P_L - Q sin^2 theta_W), Q = -1, T3 = -1/2,
+            # g = e / sin theta_W; sin^2 theta_W = 1 - M_W^2 / M_Z^2
+            sw2 = 1.0 - EW_MW ** 2 / EW_MZ ** 2
+            gz = 1.0 / (sw2 * (1.0 - sw2)) ** 0.5
+            cl, cr = -0.5 + sw2, sw2
+            out.append(f"    const W4<R> w5 = jf_chiral<R>(w0, w1, PM(0) + PM(1), gs * {gz!r}, {cl!r}, {cr!r}, "
+                       f"{EW_MZ!r}, {EW_WZ!r});")
+            out.append(f"    a = amp_ffv_chiral<R>(w3, w2, w5, gs * {gz!r}, {cl!r}, {cr!r});")
+            out.append("    SDEACC(1, 1.0);")
+            out.append("    JADD(0, 0, a.r); JADD(0, 1, a.i);")
+            fl += FLOPS["jf_chiral"] + FLOPS["amp_ffv_chiral"] + FLOPS["jamp"]
+        return fl
 
     # -----------------------------------------------------------------------------------
     def source(self, jamps_in_lds=None, remat_ext=None, jamp_mode="auto"):

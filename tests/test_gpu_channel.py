@@ -32,8 +32,11 @@ def test_channel_weights_match_oracle(name, n_evt, n_chan):
     got = proc.sigma_channel(x, ch).cpu().numpy().reshape(n_evt, len(chans))
     me = proc.sigma(torch.from_numpy(p).cuda()).cpu().numpy()
     K = Dg.colour_weights_K(name)
+    # the oracle's own helicity filter (same recipe as the library's pre-pass)
+    good = oracle.good_helicities(name, W.sqrt_s(name), W.final_masses(name), W.PARAMS)
+    assert sorted(proc.good_helicities_index()) == good
     for e in range(n_evt):
-        Wd = Dg.diagram_weights(name, p[e], W.PARAMS, K)
+        Wd = Dg.diagram_weights(name, p[e], W.PARAMS, K, helicities=good)
         tot = sum(Wd.values())
         for k, c in enumerate(chans):
             want = me[e] * Wd[lines[c]] / tot
@@ -86,3 +89,22 @@ def test_channel_rejects():
     tt = make_process("gg_tt")
     host = np.zeros(4, dtype=np.int32)
     assert L.me_sigma_channel(tt._h, v(x), 4, ctypes.c_void_p(host.ctypes.data), v(out), None) == -1
+
+
+def test_channel_weights_ee_mumu_z():
+    """photon (diagram 0) and Z (diagram 1): W_d = sum_h |A_d|^2 from the oracle's amplitudes
+    of each diagram alone"""
+    name = "ee_mumu_z"
+    proc = make_process(name)
+    assert proc.info["n_diagrams"] == 2
+    for rs in (500.0, 91.188):
+        p = oracle.rambo(44, rs, [0.0, 0.0], 8)
+        x = torch.from_numpy(np.repeat(p, 2, axis=0)).cuda()
+        ch = torch.from_numpy(np.tile(np.array([0, 1], dtype=np.int32), 8)).cuda()
+        got = proc.sigma_channel(x, ch).cpu().numpy().reshape(8, 2)
+        me = proc.sigma(torch.from_numpy(p).cuda()).cpu().numpy()
+        for e in range(8):
+            wg = sum(abs(oracle.ee_z_amplitude(p[e], h, 1, W.PARAMS)) ** 2 for h in range(16))
+            wz = sum(abs(oracle.ee_z_amplitude(p[e], h, 2, W.PARAMS)) ** 2 for h in range(16))
+            assert got[e, 0] == pytest.approx(me[e] * wg / (wg + wz), rel=1e-12)
+            assert got[e, 1] == pytest.approx(me[e] * wz / (wg + wz), rel=1e-12)

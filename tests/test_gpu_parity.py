@@ -39,7 +39,7 @@ def check_fp64(name, p, got):
 
 
 CASES = [("ee_mumu", 8192), ("gg_tt", 4093), ("gg_ttg", 1031), ("gg_ttgg", 157), ("gg_ttggg", 37),
-         ("gg_gg", 1000)]
+         ("gg_gg", 1000), ("ee_mumu_z", 8192)]
 
 
 @pytest.mark.parametrize("name,n", CASES)

@@ -177,7 +177,7 @@ def rotate(p, axis, ang):
     return out
 
 
-@pytest.mark.parametrize("proc", W.ALL + ["gg_gg"])
+@pytest.mark.parametrize("proc", W.ALL + ["gg_gg", "ee_mumu_z"])
 def test_lorentz_invariance(proc):
     p = oracle.rambo(19, W.sqrt_s(proc), W.final_masses(proc), 3 if proc != "gg_ttggg" else 1)
     for ev in p:
@@ -210,7 +210,7 @@ def test_polarisation_basis_independence(proc):
         assert oracle.me(proc, ev, basis=1) == pytest.approx(oracle.me(proc, ev), rel=1e-12)
 
 
-@pytest.mark.parametrize("proc", W.ALL + ["gg_gg"])
+@pytest.mark.parametrize("proc", W.ALL + ["gg_gg", "ee_mumu_z"])
 def test_long_double_build_agrees(proc):
     p = oracle.rambo(31, W.sqrt_s(proc), W.final_masses(proc), 2 if proc != "gg_ttggg" else 1)
     for ev in p:
@@ -236,3 +236,30 @@ def test_oracle_alpha_s_power(name):
         a = oracle.me(name, ev, params=(W.M_TOP, W.ALPHA_EM, 0.118))
         b = oracle.me(name, ev, params=(W.M_TOP, W.ALPHA_EM, 0.2))
         assert b / a == pytest.approx((0.2 / 0.118) ** n, rel=1e-12)
+
+
+@pytest.mark.parametrize("rs", [500.0, 91.188, 200.0, 60.0])
+def test_ee_mumu_z_closed_form(rs):
+    """e+e- -> mu+mu- through photon and Z, massless: the textbook helicity amplitudes
+    |M_ij|^2 = |A_ij|^2 (1 +- cos)^2 (+ when e- and mu- have the same helicity), with
+    A_ij = e^2 Q_e Q_mu + (e^2 / (s_W^2 c_W^2)) g_i g_j s / (s - M_Z^2 + i M_Z Gamma_Z),
+    g_L = T3 - Q s_W^2, g_R = -Q s_W^2; averaged |M|^2 = (1/4) sum_ij |M_ij|^2"""
+    MZ, WZ, MW = 91.188, 2.441404, 80.419
+    sw2 = 1 - MW ** 2 / MZ ** 2
+    e2 = 4 * np.pi * W.ALPHA_EM
+    gl, gr = -0.5 + sw2, sw2
+    p = oracle.rambo(6, rs, [0.0, 0.0], 6)
+    for ev in p:
+        s = rs * rs
+        chi = s / (s - MZ ** 2 + 1j * MZ * WZ)
+        pe, pm = ev[1, 1:], ev[3, 1:]
+        c = pe @ pm / (np.linalg.norm(pe) * np.linalg.norm(pm))
+        tot = 0.0
+        for gi in (gl, gr):
+            for gj in (gl, gr):
+                A = e2 + e2 / (sw2 * (1 - sw2)) * gi * gj * chi
+                tot += abs(A) ** 2 * (1 + (c if gi == gj else -c)) ** 2
+        assert oracle.me("ee_mumu_z", ev, params=W.PARAMS) == pytest.approx(tot / 4, rel=1e-12)
+        # photon only: the ee_mumu process
+        assert abs(oracle.ee_z_amplitude(ev, 0b0101, 1, W.PARAMS)) ** 2 == pytest.approx(
+            abs(oracle.ee_z_amplitude(ev, 0b1010, 1, W.PARAMS)) ** 2, rel=1e-12)

@@ -17,6 +17,7 @@ PROCESSES = {
     "gg_ttgg": ((M_TOP, M_TOP, 0.0, 0.0), 1500.0, 1 << 19),
     "gg_ttggg": ((M_TOP, M_TOP, 0.0, 0.0, 0.0), 1500.0, 1 << 18),
     "gg_gg": ((0.0, 0.0), 1500.0, 0),
+    "ee_mumu_z": ((0.0, 0.0), 500.0, 8192),
 }
 QCD = ["gg_tt", "gg_ttg", "gg_ttgg", "gg_ttggg"]
 ALL = ["ee_mumu"] + QCD

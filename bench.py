@@ -288,11 +288,13 @@ def main():
         rel = np.abs(got / me_cpu - 1)
         # events beyond the FP64 tolerance go to the referee (long double + FP64 spread)
         over = np.where(rel > 1e-12)[0]
-        referee_ok, worst = 0, []
+        referee_ok, worst, detail = 0, [], []
         for i in over:
             ok, r, spread = referee.judge(name, p[i], got[i], W.PARAMS)
             referee_ok += ok
             worst.append((r, spread, int(i)))
+            detail.append({"event": int(i), "gpu": float(got[i]), "oracle": float(me_cpu[i]),
+                           "rel_vs_long_double": r, "fp64_spread": spread, "accepted": bool(ok)})
         worst.sort(reverse=True)
         import oracle
         n1 = max(1, min(len(p), int(rate / threads * 2.0)))
@@ -306,7 +308,8 @@ def main():
                                    "median_rel_err": float(np.median(rel)), "tolerance": 1e-12,
                                    "n_over_tolerance": int(len(over)),
                                    "n_over_tolerance_within_fp64_conditioning": int(referee_ok),
-                                   "worst_rel_vs_long_double_and_fp64_spread": worst[:3]}
+                                   "worst_rel_vs_long_double_and_fp64_spread": worst[:3],
+                                   "over_tolerance": detail[:64]}
         log(f"cpu oracle: {rate:.4g} MEs/s on {threads} threads ({len(p)} events); GPU vs oracle max rel {rel.max():.2e}")
 
     print(json.dumps(result), flush=True)

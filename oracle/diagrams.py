@@ -170,10 +170,10 @@ def program(diagram, assign):
     return prog
 
 
-def lorentz(process, p, h, diagram, assign, params=None):
+def lorentz(process, p, h, diagram, assign, params=None, precision="double"):
     prog = np.ascontiguousarray(program(diagram, assign), dtype=np.int32)
     out = np.zeros(2)
-    rc = lib().or_tree_amp(PROCESSES[process], _ptr(_params(params)), _ptr(np.ascontiguousarray(p, dtype=np.float64)),
+    rc = lib(precision).or_tree_amp(PROCESSES[process], _ptr(_params(params)), _ptr(np.ascontiguousarray(p, dtype=np.float64)),
                            h, _ptr(prog, _I), len(prog), _ptr(out))
     if rc != 0:
         raise ValueError("malformed diagram program")
@@ -277,3 +277,58 @@ def channel_factor(process, p, channel_descriptor, params=None, K=None, heliciti
     """W_c / sum_d W_d for the diagram with the given internal lines"""
     W = diagram_weights(process, p, params, K, helicities)
     return W[channel_descriptor] / sum(W.values())
+
+
+# ----------------------------------------------------------------------------------------
+# the matrix element as a sum of Feynman diagrams (the GPU's algorithm, evaluated by the
+# oracle's own machinery): conditioning of that algorithm in FP64
+
+_FLOWS = {}
+
+
+def flow_coefficients(process):
+    """c[e, sigma] with CF_e = sum_sigma c[e, sigma] (t^{a_sigma1} .. t^{a_sigman})_{ij}: each
+    entry's colour tensor projected on the colour strings of ``orderings`` (least squares,
+    exact for tree diagrams)"""
+    if process not in _FLOWS:
+        from . import orderings
+        ng = n_par(process) - 2
+        t = _colour_tables()["t"]
+        strings = []
+        for sigma in orderings(process):
+            # T[i, j, a_0 .. a_{ng-1}] = (t^{a_sigma1} .. t^{a_sigman})_{ij}
+            T = None
+            for k in sigma:
+                k = int(k)
+                # factor t^{a_k}[x, y] with its own colour axis, placed at gluon k's position
+                if T is None:
+                    T = np.moveaxis(t, 0, 2)                                # [i, y, a_k]
+                    axes = [k]
+                else:
+                    T = np.tensordot(T, t, axes=([1], [1]))                 # [i, a..., b, y]
+                    T = np.moveaxis(T, -1, 1)                               # [i, y, a..., b]
+                    axes.append(k)
+            perm = [0, 1] + [2 + axes.index(g) for g in range(ng)]
+            strings.append(np.transpose(T, perm).ravel())
+        S = np.array(strings).T                                             # [colours, flows]
+        CF = np.array([colour_tensor(d, s, ng).ravel() for d, s in entries(process)]).T
+        c, *_ = np.linalg.lstsq(S, CF, rcond=None)
+        assert np.allclose(S @ c, CF, atol=1e-12)
+        _FLOWS[process] = c.T                                               # [entries, flows]
+    return _FLOWS[process]
+
+
+def diagram_me(process, p, params=None, precision="double"):
+    """averaged |M|^2 from the Feynman diagrams: jamps J_sigma = sum_e c[e, sigma] L_e (all
+    helicities), colour sum with the oracle's numeric colour matrix; the Lorentz parts in the
+    given precision of the C oracle, the jamp and colour sums in FP64"""
+    from . import colour_matrix
+    c = flow_coefficients(process)
+    C = colour_matrix(process)
+    ents = entries(process)
+    tot = 0.0
+    for h in range(1 << n_par(process)):
+        L = np.array([lorentz(process, p, h, d, s, params, precision) for d, s in ents])
+        J = L @ c
+        tot += float(np.real(np.conj(J) @ C @ J))
+    return tot / 256

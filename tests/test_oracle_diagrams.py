@@ -56,3 +56,22 @@ def test_channel_weights_sum_to_one(name):
     assert len(Wd) == {"gg_tt": 3, "gg_ttg": 16}[name]
     f = np.array(list(Wd.values())) / sum(Wd.values())
     assert np.all(f > 0) and f.sum() == pytest.approx(1.0, rel=1e-14)
+
+
+@pytest.mark.parametrize("name", ["gg_tt", "gg_ttg", "gg_ttgg"])
+def test_diagram_jamps_equal_berends_giele_partials(name):
+    """projecting every diagram's colour tensor on the colour strings gives flow
+    coefficients whose jamps sum_e c[e, sigma] L_e equal the Berends-Giele colour-ordered
+    amplitudes A(sigma) flow by flow (two algorithms of the oracle); the diagram-sum |M|^2
+    equals the oracle's"""
+    p = oracle.rambo(7, 1500.0, W.final_masses(name), 1)[0]
+    c = Dg.flow_coefficients(name)
+    ents = Dg.entries(name)
+    nh = 1 << oracle.n_par(name)
+    scale = np.sqrt(oracle.me(name, p, params=W.PARAMS) * 256 / nh)   # typical |A| (helicities can vanish)
+    for h in (0, 5, nh - 3):
+        L = np.array([Dg.lorentz(name, p, h, d, s, W.PARAMS) for d, s in ents])
+        J = L @ c
+        A = oracle.partials(name, p, h, params=W.PARAMS)
+        assert np.max(np.abs(J - A)) <= 1e-12 * scale
+    assert Dg.diagram_me(name, p, W.PARAMS) == pytest.approx(oracle.me(name, p, params=W.PARAMS), rel=1e-12)

@@ -21,7 +21,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# published context numbers for this exact workload (V100, gg->ttgg, grid 524288)
+# the paper's FP64 figure for this exact workload (Table 2: V100, gg->ttgg, grid 524288); context only
 PAPER_FP64_MES = 4.20e5
 FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 FP32_VALU_PEAK_TFLOPS = 78.6   # same without packed FP32 (disabled in this build)

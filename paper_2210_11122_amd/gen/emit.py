@@ -28,7 +28,10 @@ FLOPS = {
 
 QCD_PROCESSES = {"gg_tt": 2, "gg_ttg": 3, "gg_ttgg": 4, "gg_ttggg": 5}
 # name -> (segment kernels, LDS jamp-window slots, weight of window misses in the schedule)
-SEGMENTS = {"gg_ttggg": (8, 24, 1.0)}
+SEGMENTS = {"gg_ttggg": (14, 24, 1.0)}
+# name -> minimum waves per SIMD asked of the compiler for the (FP64, FP32) amplitude kernels
+# (the second __launch_bounds__ argument: it caps the registers per lane at 512 / waves)
+MIN_WAVES = {"gg_ttgg": (1, 2), "gg_ttggg": (1, 2)}
 ALL_PROCESSES = ["ee_mumu", "gg_tt", "gg_ttg", "gg_ttgg", "gg_ttggg", "gg_gg", "ee_mumu_z"]
 # electroweak constants of ee -> mumu with Z exchange: M_Z, Gamma_Z, M_W [GeV]
 EW_MZ, EW_WZ, EW_MW = 91.188, 2.441404, 80.419
@@ -510,7 +513,9 @@ class Process:
         sums of the segments before them."""
         L = []
         L.append("template <class R, bool SDE>")
-        L.append(f"__global__ __launch_bounds__(64) void {kname}(const double* __restrict__ mom, int64_t n_evt, "
+        w64, w32 = MIN_WAVES.get(self.name, (1, 1))
+        bounds = "64" if (w64, w32) == (1, 1) else f"64, (sizeof(R) == 8 ? {w64} : {w32})"
+        L.append(f"__global__ __launch_bounds__({bounds}) void {kname}(const double* __restrict__ mom, int64_t n_evt, "
                  "int64_t ld, const signed char* __restrict__ hel, int n_good, double mt, double gs, "
                  "R* __restrict__ jamp, const int* __restrict__ chan, double* __restrict__ sde)")
         L.append("{")
@@ -649,7 +654,11 @@ def generate(outdir, names=None):
             continue
         P = Process(nm)
         src = P.source()
-        for fname, fsrc in getattr(P, "extra_files", {}).items():
+        extra = getattr(P, "extra_files", {})
+        for stale in os.listdir(outdir):
+            if stale.startswith(f"proc_{nm}_amp_seg") and stale not in extra:
+                os.remove(os.path.join(outdir, stale))
+        for fname, fsrc in extra.items():
             fpath = os.path.join(outdir, fname)
             if not os.path.exists(fpath) or open(fpath).read() != fsrc:
                 with open(fpath, "w") as f:

@@ -95,9 +95,10 @@ __device__ __forceinline__ void cs_store(double me, int64_t e, int64_t n_evt, do
 }
 
 // A operands, per lane, in the kernel's tile order (mt ascending, then kt >= 4 mt):
-// aop[q * 64 + l] = A[16 mt + l % 16][4 kt + l / 16].
-template <int NC>
-__global__ __launch_bounds__(256) void colour_sum_f64(const double* __restrict__ J, int64_t ld, int n_good,
+// aop[q * 64 + l] = A[16 mt + l % 16][4 kt + l / 16].  JT: the jamps' storage type (float for the
+// mixed forms' small colour matrices, which a 16x16x32 tile would mostly pad with zeros).
+template <int NC, class JT = double>
+__global__ __launch_bounds__(256) void colour_sum_f64(const JT* __restrict__ J, int64_t ld, int n_good,
                                                       int hel_per_group, int64_t n_evt,
                                                       const double* __restrict__ aop, double scale_hel,
                                                       double scale_avg, double* __restrict__ out,
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(256) void colour_sum_f64(const double* __restrict__
     }
     double me = 0.0;
     for (int h = h0; h < h1; ++h) {
-        const double* Jh = J + (int64_t)h * (2 * NC) * ld;
+        const JT* Jh = J + (int64_t)h * (2 * NC) * ld;
         double part_h = 0.0;
 #pragma unroll 1
         for (int ri = 0; ri < 2; ++ri) {
@@ -129,7 +130,7 @@ __global__ __launch_bounds__(256) void colour_sum_f64(const double* __restrict__
 #pragma unroll
             for (int kt = 0; kt < KT; ++kt) {
                 const int c = 4 * kt + g;
-                b[kt] = (c < NC) ? Jh[(int64_t)(2 * c + ri) * ld + ec] : 0.0;
+                b[kt] = (c < NC) ? (double)Jh[(int64_t)(2 * c + ri) * ld + ec] : 0.0;
             }
             int q = 0;
 #pragma unroll

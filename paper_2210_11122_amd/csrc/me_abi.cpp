@@ -112,11 +112,11 @@ struct ColourArgs {
     double *out, *out_hel, *part;
 };
 
-template <int NC>
-hipError_t launch_cs64(const double* J, const double* aop, const ColourArgs& a, hipStream_t st)
+template <int NC, class JT = double>
+hipError_t launch_cs64(const JT* J, const double* aop, const ColourArgs& a, hipStream_t st)
 {
-    hipLaunchKernelGGL(me::colour_sum_f64<NC>, dim3((unsigned)((a.n + 63) / 64), (unsigned)a.groups), dim3(256), 0,
-                       st, J, a.ld, a.n_good, a.hel_per_group, a.n, aop, a.scale_hel, a.scale_avg, a.out, a.out_hel,
+    hipLaunchKernelGGL((me::colour_sum_f64<NC, JT>), dim3((unsigned)((a.n + 63) / 64), (unsigned)a.groups), dim3(256),
+                       0, st, J, a.ld, a.n_good, a.hel_per_group, a.n, aop, a.scale_hel, a.scale_avg, a.out, a.out_hel,
                        a.part);
     return hipGetLastError();
 }
@@ -133,10 +133,7 @@ template <class T>
 hipError_t dispatch_cs16(int nc, const float* j, const typename T::elem* aop, const typename T::elem* aop_lo,
                          uint64_t lo_mask, const ColourArgs& a, hipStream_t st)
 {
-    switch (nc) {
-    case 1: return launch_cs16<1, T>(j, aop, aop_lo, lo_mask, a, st);
-    case 2: return launch_cs16<2, T>(j, aop, aop_lo, lo_mask, a, st);
-    case 6: return launch_cs16<6, T>(j, aop, aop_lo, lo_mask, a, st);
+    switch (nc) {  // N_c <= 6 goes to the FP64 matrix cores (colour_sum)
     case 24: return launch_cs16<24, T>(j, aop, aop_lo, lo_mask, a, st);
     case 120: return launch_cs16<120, T>(j, aop, aop_lo, lo_mask, a, st);
     }
@@ -159,6 +156,15 @@ hipError_t colour_sum(const me_handle* h, int precision, const void* J, int64_t 
         case 6: e = launch_cs64<6>(j, h->d_aop64, a, st); break;
         case 24: e = launch_cs64<24>(j, h->d_aop64, a, st); break;
         case 120: e = launch_cs64<120>(j, h->d_aop64, a, st); break;
+        }
+    } else if (h->P->nc <= 6) {
+        // mixed forms, small colour matrices: the FP32 jamps on the FP64 matrix cores (a 16x16x32
+        // tile would be mostly padding; this is faster there and exact up to FP64 rounding)
+        const float* j = static_cast<const float*>(J);
+        switch (h->P->nc) {
+        case 1: e = launch_cs64<1, float>(j, h->d_aop64, a, st); break;
+        case 2: e = launch_cs64<2, float>(j, h->d_aop64, a, st); break;
+        case 6: e = launch_cs64<6, float>(j, h->d_aop64, a, st); break;
         }
     } else if (precision == ME_MIXED_FP16) {
         e = dispatch_cs16<me::Fp16Terms>(h->P->nc, static_cast<const float*>(J), h->d_aop16, h->d_aop16, 0, a, st);
@@ -234,7 +240,6 @@ struct TimedLaunch {
     }
 };
 
-// amplitude kernel + colour sum for events [0, n) of `mom`, in chunks through `jamp`
 // per-event strong coupling: every tree amplitude of a pure-QCD process carries g_s^(n_par - 2)
 // (a three-gluon or quark-gluon vertex one power, the four-gluon vertex two), so |M|^2 computed
 // at the handle's alpha_s becomes the per-event value through the factor (a_e / a_0)^(n_par - 2)
@@ -271,7 +276,9 @@ struct Selection {
     double *hel_me, *w;
 };
 
-// scratch: jamps of `chunk` events (jamp_bytes_per_event each), then the helicity-group partial sums
+// amplitude kernel + colour sum (+ the optional per-event kernels) for events [0, n) of `mom`, in
+// chunks; scratch: jamps of `chunk` events (jamp_bytes_per_event each), then the helicity-group
+// partial sums
 int run_chunks(me_handle* h, int precision, const signed char* hel, int n_good, int hel_per_group, int groups,
                int64_t chunk, size_t jamp_bytes_per_event, const double* mom, int64_t n, double* out, double* out_hel,
                void* scratch, hipStream_t st, bool timed = false, const Selection* sel = nullptr,

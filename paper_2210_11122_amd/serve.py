@@ -111,14 +111,19 @@ class Scheduler:
             self.free_slots.append(slot)
             self.done.append(c)
 
-    def run(self, requests, keep_results=False):
+    def run(self, requests, keep_results=False, progress=None, progress_every=20.0):
         """Drive the requests (sorted by arrival, times relative to the start) to
-        completion; returns the list of Completed."""
+        completion; returns the list of Completed.  progress(elapsed, done, total) is
+        called every progress_every seconds of the executor's clock."""
         reqs = sorted(requests, key=lambda r: r.arrival)
         t0 = self.ex.now()
+        next_report = progress_every
         i = 0
         while i < len(reqs) or self.pending or self.running:
             now = self.ex.now() - t0
+            if progress is not None and now >= next_report:
+                progress(now, len(self.done), len(reqs))
+                next_report += progress_every
             while i < len(reqs) and reqs[i].arrival <= now:
                 r = reqs[i]
                 self.submit(r._replace(arrival=t0 + r.arrival))
@@ -274,7 +279,7 @@ def bench_serving(duration_s=10.0, processes=("gg_tt", "gg_ttg", "gg_ttgg"), n_s
         reqs = poisson_requests(n, rate, list(processes), seed=1)
         sch = Scheduler(ex, n_slots, hbm_budget)
         t = time.perf_counter()
-        done = sch.run(reqs)
+        done = sch.run(reqs, progress=lambda el, nd, nt: log(f"serving load {load}: {el:.0f} s, {nd}/{nt} done"))
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
         st = latency_stats(done)

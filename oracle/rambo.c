@@ -118,9 +118,10 @@ int or_rambo_event(uint64_t seed, double sqrt_s, int n_final, const double *mass
     }
 
     /* step 3: massive particles.  Solve sum_i sqrt(m_i^2 + xi^2 E_i^2) = sqrt(s) for xi
-     * (E_i = |p_i| of the massless momenta), starting from the value given in the RAMBO
-     * paper, xi0 = sqrt(1 - (sum m / sqrt s)^2); stop when the residual is at most
-     * 1e-14 sqrt(s) or after 50 steps. */
+     * (E_i = |p_i| of the massless momenta) by Newton's method, starting from the value given
+     * in the RAMBO paper, xi0 = sqrt(1 - (sum m / sqrt s)^2), until the residual stops
+     * decreasing (its rounding floor: energy then balances to a few ulp of sqrt(s)) or after
+     * 50 steps; the xi of the smallest residual is used. */
     double msum = 0.0;
     int massive = 0;
     for (int i = 0; i < n_final; ++i) {
@@ -130,6 +131,7 @@ int or_rambo_event(uint64_t seed, double sqrt_s, int n_final, const double *mass
     int iters = 0;
     if (massive) {
         double xi = sqrt(1.0 - (msum / sqrt_s) * (msum / sqrt_s));
+        double xi_best = xi, r_best = INFINITY;
         for (iters = 0; iters < 50; ++iters) {
             double f = -sqrt_s, fp = 0.0;
             for (int i = 0; i < n_final; ++i) {
@@ -137,9 +139,13 @@ int or_rambo_event(uint64_t seed, double sqrt_s, int n_final, const double *mass
                 f += e;
                 fp += xi * p[i][0] * p[i][0] / e;
             }
-            if (fabs(f) <= 1e-14 * sqrt_s) break;
+            if (!(fabs(f) < r_best)) break;
+            r_best = fabs(f);
+            xi_best = xi;
+            if (f == 0.0) break;
             xi -= f / fp;
         }
+        xi = xi_best;
         for (int i = 0; i < n_final; ++i) {
             double e = sqrt(masses[i] * masses[i] + xi * xi * p[i][0] * p[i][0]);
             p[i][0] = e;

@@ -6,8 +6,8 @@
 // Momenta: RAMBO (Kleiss, Stirling, Ellis, Comput. Phys. Commun. 40 (1986) 359) --
 // isotropic massless vectors with energy density q0 exp(-q0), conformal transformation to
 // the centre-of-mass frame at sqrt(s), then the common rescaling xi that puts massive
-// particles on shell (Newton's method from the paper's starting value, residual below
-// 1e-14 sqrt(s) or 50 steps).  Output layout [event][particle][E, px, py, pz] with the two
+// particles on shell (Newton's method from the paper's starting value until the residual
+// stops decreasing, at most 50 steps).  Output layout [event][particle][E, px, py, pz] with the two
 // beams along +z and -z first.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -87,6 +87,7 @@ __global__ __launch_bounds__(256) void rambo_kernel(uint64_t seed, double sqrt_s
     }
     if (massive) {
         double xi = sqrt(1.0 - (msum / sqrt_s) * (msum / sqrt_s));
+        double xi_best = xi, r_best = INFINITY;
         for (int it = 0; it < 50; ++it) {
             double f = -sqrt_s, fp = 0.0;
 #pragma unroll
@@ -95,9 +96,14 @@ __global__ __launch_bounds__(256) void rambo_kernel(uint64_t seed, double sqrt_s
                 f += e;
                 fp += xi * p[i][0] * p[i][0] / e;
             }
-            if (fabs(f) <= 1e-14 * sqrt_s) break;
+            // Newton until the residual stops decreasing (its rounding floor), keeping the best xi
+            if (!(fabs(f) < r_best)) break;
+            r_best = fabs(f);
+            xi_best = xi;
+            if (f == 0.0) break;
             xi -= f / fp;
         }
+        xi = xi_best;
 #pragma unroll
         for (int i = 0; i < NF; ++i) {
             p[i][0] = sqrt(mass[i] * mass[i] + xi * xi * p[i][0] * p[i][0]);

@@ -28,9 +28,13 @@
  *     the colour matrix C = sum over explicit colour indices of (T^sigma)(T^tau)^*,
  *     summed numerically with the Gell-Mann matrices;
  *   - gg -> gg (a test process): the single-trace decomposition with leg 4 fixed last;
- *   - e+e- -> mu+mu-: the one photon diagram written out as a spinor sandwich;
+ *   - e+e- -> mu+mu-: the one photon diagram written out as a spinor sandwich, and with Z
+ *     exchange added (chiral couplings, Breit-Wigner propagator);
  *   - a colour-dressed recursion with explicit f^{abc} and t^a and explicit external
- *     colours, used to brute-force the colour sum and to spot-check the decomposition.
+ *     colours, used to brute-force the colour sum and to spot-check the decomposition;
+ *   - one Feynman diagram at a time (or_tree_amp, colour stripped): the single-diagram
+ *     channel weights and the FP64 conditioning of a diagram sum are built on it in
+ *     oracle/diagrams.py, with its own diagram enumeration and numeric colour factors.
  * External states are helicity eigenstates (the HELAS conventions: Hagiwara, Murayama,
  * Watanabe, KEK-91-11), plus a second basis (linear gluon polarisations, top spin along z
  * in the rest frame) for basis-independence checks.

@@ -22,8 +22,8 @@
 // Mixed forms: the FP32 real (imaginary) rows of one (event, helicity) column are scaled by
 // a power of two so that their largest |J| lies in [1/2, 1), split exactly into two 16-bit
 // terms hi + lo * 2^-p (p = 11 for FP16, 8 for BF16), and contracted with
-// v_mfma_f32_16x16x32_{f16,bf16} (FP32 accumulation); the dot product is formed in FP32 from
-// the scaled FP32 jamps, unscaled exactly, and summed over helicities in FP64.  Colour
+// v_mfma_f32_16x16x32_{f16,bf16} (FP32 accumulation); the dot product with the scaled FP32
+// jamps is formed in FP64, unscaled exactly, and summed over helicities in FP64.  Colour
 // numerators that a 16-bit type cannot hold exactly (BF16 keeps 8 significant bits) are
 // split the same way on the host into A_hi + A_lo, both exact; tiles whose A_lo vanishes
 // are skipped by a per-tile mask.
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(256) void colour_sum_h16(const float* __restrict__ 
                     bl[kb][t] = T::round((v - T::value(hi)) * T::LO);
                     x[kb][t] = v;
                 }
-            float acc = 0.0f;
+            double acc = 0.0;  // the column dot product, in FP64 (colour sums can cancel)
             int q = 0;
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
@@ -259,9 +259,10 @@ __global__ __launch_bounds__(256) void colour_sum_h16(const float* __restrict__ 
                 }
                 // D rows 16 mt + 4 g + r are this lane's x[mt / 2][4 (mt % 2) + r]
 #pragma unroll
-                for (int r = 0; r < 4; ++r) acc += x[mt / 2][4 * (mt % 2) + r] * (dh[r] + dl[r] * (1.0f / T::LO));
+                for (int r = 0; r < 4; ++r)
+                    acc += (double)x[mt / 2][4 * (mt % 2) + r] * ((double)dh[r] + (double)dl[r] * (1.0 / T::LO));
             }
-            part_h += (double)acc / ((double)s * (double)s);
+            part_h += acc / ((double)s * (double)s);
         }
         part_h = sum_lane_groups(part_h);
         if (out_hel && g == 0 && valid) out_hel[e * n_good + h] = part_h * scale_hel;

@@ -414,7 +414,9 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t w, int64_t n)
 }
 
 // Stage the momenta of events [e0, e0+64) (layout [event][particle][4], double) through
-// LDS with coalesced 16-byte loads, into lds[component][lane]; lanes past n_evt read zeros.
+// LDS with coalesced 16-byte loads, into component pairs lds2[2 i + (E, px) | (py, pz)][lane]
+// (16 bytes per lane, so a lane reads a four-momentum with two conflict-free 16-byte LDS
+// loads); lanes past n_evt read zeros.
 template <int NPAR>
 __device__ __forceinline__ void stage_momenta(const double* __restrict__ mom, int64_t n_evt, int64_t e0,
                                               double* lds, int lane)
@@ -429,8 +431,7 @@ __device__ __forceinline__ void stage_momenta(const double* __restrict__ mom, in
         int c = (2 * f) % NCOMP;      // first component
         double2 v = {0.0, 0.0};
         if (ev < n_here) v = src[f];
-        lds[c * 64 + ev] = v.x;
-        lds[(c + 1) * 64 + ev] = v.y;
+        reinterpret_cast<double2*>(lds)[(c / 2) * 64 + ev] = v;   // c is even: one component pair
     }
     __syncthreads();
 }
@@ -442,10 +443,11 @@ namespace me {
 // use (volatile: the compiler neither caches nor hoists it, so no four-momentum stays live)
 __device__ __forceinline__ P4 lds_p4(const double* lds, int i, int lane)
 {
-    typedef __attribute__((address_space(3))) const volatile double lds_double;
-    lds_double* v = (lds_double*)lds;
-    return {v[(4 * i) * 64 + lane], v[(4 * i + 1) * 64 + lane], v[(4 * i + 2) * 64 + lane],
-            v[(4 * i + 3) * 64 + lane]};
+    typedef double v2d __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(3))) const volatile v2d lds_v2d;
+    lds_v2d* v = (lds_v2d*)lds;
+    const v2d a = v[(2 * i) * 64 + lane], b = v[(2 * i + 1) * 64 + lane];
+    return {a.x, a.y, b.x, b.y};
 }
 // LDS atomic add into this lane's private jamp slot (no return value: ds_add_f64 / ds_add_f32)
 template <class R>

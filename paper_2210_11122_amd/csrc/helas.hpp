@@ -42,6 +42,17 @@ __device__ __forceinline__ cx<R> operator*(R s, cx<R> a) { return {s * a.r, s * 
 // i * a
 template <class R>
 __device__ __forceinline__ cx<R> mul_i(cx<R> a) { return {-a.i, a.r}; }
+// c + a b and c - a b as chains of fused multiply-adds (4 instead of 2 mul + 2 fma + 2 add)
+template <class R>
+__device__ __forceinline__ cx<R> cfma(cx<R> a, cx<R> b, cx<R> c)
+{
+    return {fma(a.r, b.r, fma(-a.i, b.i, c.r)), fma(a.r, b.i, fma(a.i, b.r, c.i))};
+}
+template <class R>
+__device__ __forceinline__ cx<R> cfms(cx<R> a, cx<R> b, cx<R> c)
+{
+    return {fma(-a.r, b.r, fma(a.i, b.i, c.r)), fma(-a.r, b.i, fma(-a.i, b.r, c.i))};
+}
 
 struct P4 {
     double t, x, y, z;
@@ -84,7 +95,7 @@ struct W4 {
 template <class R>
 __device__ __forceinline__ cx<R> dot(const W4<R>& a, const W4<R>& b)
 {
-    return a.c[0] * b.c[0] - a.c[1] * b.c[1] - a.c[2] * b.c[2] - a.c[3] * b.c[3];
+    return cfms(a.c[3], b.c[3], cfms(a.c[2], b.c[2], cfms(a.c[1], b.c[1], a.c[0] * b.c[0])));
 }
 // real vector in the working precision
 template <class R>
@@ -214,10 +225,10 @@ __device__ __forceinline__ W4<R> gslash_col(const W4<R>& G, const W4<R>& s)
     cx<R> a = G.c[0] + G.c[3], b = G.c[0] - G.c[3];
     cx<R> c = G.c[1] + mul_i(G.c[2]), d = G.c[1] - mul_i(G.c[2]);
     W4<R> o;
-    o.c[0] = b * s.c[2] - d * s.c[3];
-    o.c[1] = a * s.c[3] - c * s.c[2];
-    o.c[2] = a * s.c[0] + d * s.c[1];
-    o.c[3] = c * s.c[0] + b * s.c[1];
+    o.c[0] = cfms(d, s.c[3], b * s.c[2]);
+    o.c[1] = cfms(c, s.c[2], a * s.c[3]);
+    o.c[2] = cfma(d, s.c[1], a * s.c[0]);
+    o.c[3] = cfma(b, s.c[1], c * s.c[0]);
     return o;
 }
 // ubar (gamma.G) for a row spinor
@@ -227,10 +238,10 @@ __device__ __forceinline__ W4<R> gslash_row(const W4<R>& u, const W4<R>& G)
     cx<R> a = G.c[0] + G.c[3], b = G.c[0] - G.c[3];
     cx<R> c = G.c[1] + mul_i(G.c[2]), d = G.c[1] - mul_i(G.c[2]);
     W4<R> o;
-    o.c[0] = u.c[2] * a + u.c[3] * c;
-    o.c[1] = u.c[2] * d + u.c[3] * b;
-    o.c[2] = u.c[0] * b - u.c[1] * c;
-    o.c[3] = u.c[1] * a - u.c[0] * d;
+    o.c[0] = cfma(u.c[3], c, u.c[2] * a);
+    o.c[1] = cfma(u.c[3], b, u.c[2] * d);
+    o.c[2] = cfms(u.c[1], c, u.c[0] * b);
+    o.c[3] = cfms(u.c[0], d, u.c[1] * a);
     return o;
 }
 // f (qslash + m) phi for a column spinor and real q
@@ -311,7 +322,7 @@ __device__ __forceinline__ W4<R> vvv_cur(const W4<R>& J1, const P4& k1, const W4
     W4<R> o;
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
-        cx<R> v = ar[mu] * d12 + J2.c[mu] * d1b - J1.c[mu] * d2c;
+        cx<R> v = cfms(J1.c[mu], d2c, cfma(J2.c[mu], d1b, ar[mu] * d12));
         o.c[mu] = {(R)f * v.i, -(R)f * v.r};  // -i f v
     }
     return o;
@@ -326,15 +337,15 @@ __device__ __forceinline__ W4<R> vvvv_cur(const W4<R>& Ja, const W4<R>& Jb, cons
     if (S == 0) {
         cx<R> ac = dot(Ja, Jc), ab = dot(Ja, Jb);
 #pragma unroll
-        for (int mu = 0; mu < 4; ++mu) o.c[mu] = f * (Jb.c[mu] * ac - Jc.c[mu] * ab);
+        for (int mu = 0; mu < 4; ++mu) o.c[mu] = f * cfms(Jc.c[mu], ab, Jb.c[mu] * ac);
     } else if (S == 1) {
         cx<R> bc = dot(Jb, Jc), ab = dot(Ja, Jb);
 #pragma unroll
-        for (int mu = 0; mu < 4; ++mu) o.c[mu] = f * (Ja.c[mu] * bc - Jc.c[mu] * ab);
+        for (int mu = 0; mu < 4; ++mu) o.c[mu] = f * cfms(Jc.c[mu], ab, Ja.c[mu] * bc);
     } else {
         cx<R> bc = dot(Jb, Jc), ac = dot(Ja, Jc);
 #pragma unroll
-        for (int mu = 0; mu < 4; ++mu) o.c[mu] = f * (Ja.c[mu] * bc - Jb.c[mu] * ac);
+        for (int mu = 0; mu < 4; ++mu) o.c[mu] = f * cfms(Jb.c[mu], ac, Ja.c[mu] * bc);
     }
     return o;
 }
@@ -343,7 +354,7 @@ template <class R>
 __device__ __forceinline__ cx<R> amp_ffv(const W4<R>& u, const W4<R>& s, const W4<R>& G, double g)
 {
     W4<R> t = gslash_col<R>(G, s);
-    cx<R> x = u.c[0] * t.c[0] + u.c[1] * t.c[1] + u.c[2] * t.c[2] + u.c[3] * t.c[3];
+    cx<R> x = cfma(u.c[3], t.c[3], cfma(u.c[2], t.c[2], cfma(u.c[1], t.c[1], u.c[0] * t.c[0])));
     return (R)g * mul_i(x);
 }
 // Chiral couplings (gamma5 = diag(-1, -1, 1, 1): P_L keeps components 0, 1 of a column spinor).
@@ -384,7 +395,7 @@ __device__ __forceinline__ cx<R> amp_vvv(const W4<R>& Wx, const P4& kx, const W4
 {
     cx<R> xa = dot(Wx, Wa), ab = dot(Wa, Wb), bx = dot(Wb, Wx);
     cx<R> t1 = dot(Wb, rnd<R>(kx - ka)), t2 = dot(Wx, rnd<R>(ka - kb)), t3 = dot(Wa, rnd<R>(kb - kx));
-    return (R)g * (xa * t1 + ab * t2 + bx * t3);
+    return (R)g * cfma(bx, t3, cfma(ab, t2, xa * t1));
 }
 // amplitude of a four-gluon vertex, legs (x, a, b, c): -i g^2 times
 //   S0: (x.b)(a.c) - (x.c)(a.b);  S1: (x.a)(b.c) - (x.c)(a.b);  S2: (x.a)(b.c) - (x.b)(a.c)
@@ -393,9 +404,9 @@ __device__ __forceinline__ cx<R> amp_vvvv(const W4<R>& Wx, const W4<R>& Wa, cons
                                           double g)
 {
     cx<R> v;
-    if (S == 0) v = dot(Wx, Wb) * dot(Wa, Wc) - dot(Wx, Wc) * dot(Wa, Wb);
-    else if (S == 1) v = dot(Wx, Wa) * dot(Wb, Wc) - dot(Wx, Wc) * dot(Wa, Wb);
-    else v = dot(Wx, Wa) * dot(Wb, Wc) - dot(Wx, Wb) * dot(Wa, Wc);
+    if (S == 0) v = cfms(dot(Wx, Wc), dot(Wa, Wb), dot(Wx, Wb) * dot(Wa, Wc));
+    else if (S == 1) v = cfms(dot(Wx, Wc), dot(Wa, Wb), dot(Wx, Wa) * dot(Wb, Wc));
+    else v = cfms(dot(Wx, Wb), dot(Wa, Wc), dot(Wx, Wa) * dot(Wb, Wc));
     cx<R> iv = mul_i(v);
     return (R)(-g * g) * iv;
 }

@@ -14,6 +14,7 @@ call (complex multiply = 6, complex add = 2, real x complex = 2), plus momentum 
 four-vector addition) and jamp updates (2 per update).
 """
 import os
+import re
 from fractions import Fraction
 from itertools import permutations
 
@@ -29,6 +30,8 @@ FLOPS = {
 QCD_PROCESSES = {"gg_tt": 2, "gg_ttg": 3, "gg_ttgg": 4, "gg_ttggg": 5}
 # name -> (segment kernels, LDS jamp-window slots, weight of window misses in the schedule)
 SEGMENTS = {"gg_ttggg": (14, 24, 1.0)}
+# read each amplitude step's momenta from LDS ahead of the previous step's jamp updates
+PREFETCH_MOMENTA = True
 # name -> minimum waves per SIMD asked of the compiler for the (FP64, FP32) amplitude kernels
 # (the second __launch_bounds__ argument: it caps the registers per lane at 512 / waves)
 MIN_WAVES = {"gg_ttgg": (1, 2), "gg_ttggg": (1, 2)}
@@ -166,11 +169,19 @@ class Process:
         p = self.gpar[i]
         return f"p[{p}]" if p < 2 else f"(-p[{p}])"
 
-    def _emit_qcd_body(self, out, remat_ext, order=None, steps=None, final=None):
+    def _emit_qcd_body(self, out, remat_ext, order=None, steps=None, final=None, prefetch=None):
         """Emit the diagram program.  Momentum sums are written inline from fresh LDS reads
-        at every use (so no four-momentum stays live in registers); with remat_ext the
+        (so no four-momentum stays live in registers across the program); with remat_ext the
         external wavefunctions are recomputed at every use instead of being kept live.
+        With prefetch (default: on) the LDS reads of each amplitude step are issued as one
+        group before the previous step's amplitude and jamp updates (software pipelining):
+        a read issued after the jamps' LDS atomic adds could only complete after them, since
+        LDS operations complete in order, so every step would start with a stall.
         Returns the algorithmic flop count (each distinct node once)."""
+        if prefetch is None:
+            prefetch = PREFETCH_MOMENTA
+        body_start = len(out)
+        marks = []   # per step: (first node line, amplitude line, first jamp-update line)
         names = {}
         flops = [0]
         ksums = set()
@@ -270,8 +281,10 @@ class Process:
         for ai, (di, opt, deps) in enumerate(order):
             d = self.diagrams[di]
             kind, j = opt
+            m_node = len(out)
             if kind == "FFV":
                 wu, wv, wg = (emit(k) for k in deps)
+                m_amp = len(out)
                 out.append(f"    a = amp_ffv<R>({wu}, {wv}, {wg}, gs);")
                 flops[0] += FLOPS["amp_ffv"]
             else:
@@ -279,6 +292,7 @@ class Process:
                 kids = D.children(t)
                 wx = emit(deps[0])
                 ws = [emit(k) for k in deps[1:]]
+                m_amp = len(out)
                 if self.kind == "gluon":
                     kx = K((self.ng - 1,))
                 else:
@@ -292,6 +306,7 @@ class Process:
                     flops[0] += FLOPS["amp_vvvv"]
             if self.fd_index is not None:
                 out.append(f"    SDEACC({self.fd_index[di]}, {self.kweight[di]!r});")
+            marks.append((m_node, m_amp, len(out)))
             if steps is None:
                 for seq, c in sorted(self.jcoef[di].items()):
                     out.append(self._jamp_update(self.perm_index[seq], c))
@@ -306,6 +321,9 @@ class Process:
         if final:
             for slot, pidx, _ in final:
                 out.append(f"    JFLUSH({slot}, {pidx});")
+        if prefetch and marks:
+            out[body_start:] = _pipeline_momenta(out[body_start:], [tuple(m - body_start for m in t)
+                                                                    for t in marks])
         return flops[0]
 
     @staticmethod
@@ -632,6 +650,40 @@ class Process:
 
 # processes whose diagram program is not emitted yet: the library reports them as unknown
 NOT_EMITTED = set()
+
+
+_PM = re.compile(r"PM\((\d+)\)")
+
+
+def _pipeline_momenta(lines, marks):
+    """Rewrite a diagram program so that the momenta of amplitude step s are read from LDS
+    into registers (const P4 m<s>_<i>) at one point: before the amplitude of step s-1
+    (step 0: at its start).  marks[s] = (first node line, amplitude line, first jamp-update
+    line) of step s, indices into lines."""
+    out = []
+    used = []
+    for s, (a, b, c) in enumerate(marks):
+        ks = sorted({int(k) for ln in lines[a:c] for k in _PM.findall(ln)})
+        used.append(ks)
+
+    def decl(s):
+        return [f"    const P4 m{s}_{k} = PM({k});" for k in used[s]]
+
+    def sub(s, ln):
+        return _PM.sub(lambda m: f"m{s}_{m.group(1)}", ln)
+
+    pos = 0
+    for s, (a, b, c) in enumerate(marks):
+        out += lines[pos:a]                      # jamp updates of step s-1 (or preamble)
+        if s == 0:
+            out += decl(0)
+        out += [sub(s, ln) for ln in lines[a:b]]   # nodes of step s
+        if s + 1 < len(marks):
+            out += decl(s + 1)                   # next step's reads, ahead of this step's atomics
+        out += [sub(s, ln) for ln in lines[b:c]]   # amplitude (+ channel weight) of step s
+        pos = c
+    out += lines[pos:]
+    return out
 
 
 def stub_source(nm):

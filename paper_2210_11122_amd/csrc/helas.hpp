@@ -460,6 +460,15 @@ __device__ __forceinline__ P4 lds_p4(const double* lds, int i, int lane)
     const v2d a = v[(2 * i) * 64 + lane], b = v[(2 * i + 1) * 64 + lane];
     return {a.x, a.y, b.x, b.y};
 }
+// Marks a four-momentum as first needed here: arithmetic on it (momentum sums) cannot be
+// moved above this point, so a value read from LDS early need not be waited for earlier.
+// Only in the FP64 kernels (one wave per SIMD, nothing else hides the wait); the FP32
+// kernels run two waves per SIMD and measured faster without it.
+template <class R>
+__device__ __forceinline__ void pin_p4(P4& p)
+{
+    if constexpr (sizeof(R) == 8) asm volatile("" : "+v"(p.t), "+v"(p.x), "+v"(p.y), "+v"(p.z));
+}
 // LDS atomic add into this lane's private jamp slot (no return value: ds_add_f64 / ds_add_f32)
 template <class R>
 __device__ __forceinline__ void lds_add(R* p, R v)

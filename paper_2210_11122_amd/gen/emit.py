@@ -32,6 +32,8 @@ QCD_PROCESSES = {"gg_tt": 2, "gg_ttg": 3, "gg_ttgg": 4, "gg_ttggg": 5}
 SEGMENTS = {"gg_ttggg": (14, 24, 1.0)}
 # read each amplitude step's momenta from LDS ahead of the previous step's jamp updates
 PREFETCH_MOMENTA = True
+# and keep the compiler from summing them before the step that uses them
+PIN_MOMENTA = True
 # name -> minimum waves per SIMD asked of the compiler for the (FP64, FP32) amplitude kernels
 # (the second __launch_bounds__ argument: it caps the registers per lane at 512 / waves)
 MIN_WAVES = {"gg_ttgg": (1, 2), "gg_ttggg": (1, 2)}
@@ -182,6 +184,7 @@ class Process:
             prefetch = PREFETCH_MOMENTA
         body_start = len(out)
         marks = []   # per step: (first node line, amplitude line, first jamp-update line)
+        puts = []    # per step: the JPUT lines of the slots it evicted
         names = {}
         flops = [0]
         ksums = set()
@@ -313,17 +316,28 @@ class Process:
                     flops[0] += FLOPS["jamp"]
             else:
                 coef = {self.perm_index[seq]: c for seq, c in self.jcoef[di].items()}
+                mine = []
                 for j, slot, flush in steps[ai]:
                     if flush is not None:
-                        out.append(f"    JFLUSH({flush[0]}, {flush[1]});")
+                        k = flush[1]
+                        out.append(f"    JTAKE({flush[0]}, {k});")
+                        mine.append(f"    JPUT({k}, {k});")
                     out.append(self._jamp_update(slot, coef[j]))
                     flops[0] += FLOPS["jamp"]
+                if prefetch:
+                    puts.append(mine)
+                else:
+                    out += mine
+        tail = []
+        if puts:
+            tail += puts[-1]
         if final:
-            for slot, pidx, _ in final:
-                out.append(f"    JFLUSH({slot}, {pidx});")
+            tail += [f"    JLAST({slot}, {pidx});" for slot, pidx, _ in final]
+            tail += [f"    JPUT({pidx}, {pidx});" for slot, pidx, _ in final]
         if prefetch and marks:
             out[body_start:] = _pipeline_momenta(out[body_start:], [tuple(m - body_start for m in t)
-                                                                    for t in marks])
+                                                                    for t in marks], puts)
+        out += tail
         return flops[0]
 
     @staticmethod
@@ -523,7 +537,7 @@ class Process:
     def _kernel_text(self, kname, body, nwin, mode, jamps_in_lds, jamp_mode, first=True):
         """one amplitude kernel: momenta staging, helicity signs, jamp storage, body, output.
         mode 'jamps': the NC jamps are written at the end, layout [h][2c + re/im][column];
-        mode 'slots': the body flushes window slots to partial slots (JFLUSH), layout
+        mode 'slots': the body evicts window slots to partial slots (JTAKE, later JPUT), layout
         [h][2s + re/im][column] after the jamp region.
         With SDE the kernel also sums, per lane, the colour-summed single-diagram squares
         K_e |a_e|^2 of its amplitude entries (all, and those of the event's channel chan[e])
@@ -580,8 +594,13 @@ class Process:
             L.append("#define JGET(s, ri) Jr[2 * (s) + (ri)]")
         if mode == "slots":
             L.append("    R* const po = jamp + (int64_t)n_good * (2 * NC) * ld + (int64_t)h * (2 * NSLOT) * ld + e;")
-            L.append("#define JFLUSH(s, p) do { po[(int64_t)(2 * (p)) * ld] = JGET(s, 0); "
-                     "po[(int64_t)(2 * (p) + 1) * ld] = JGET(s, 1); JZERO(s, 0); JZERO(s, 1); } while (0)")
+            # evicting a window slot: JTAKE reads it into registers and clears it (LDS
+            # accesses complete in order, so no wait is needed there); JPUT stores the pair
+            # to its partial slot later, once the read has long completed
+            L.append("#define JTAKE(s, k) const R fr##k = JGET(s, 0), fi##k = JGET(s, 1); JZERO(s, 0); JZERO(s, 1)")
+            L.append("#define JLAST(s, k) const R fr##k = JGET(s, 0), fi##k = JGET(s, 1)")
+            L.append("#define JPUT(p, k) do { po[(int64_t)(2 * (p)) * ld] = fr##k; "
+                     "po[(int64_t)(2 * (p) + 1) * ld] = fi##k; } while (0)")
         L.append("    cx<R> a;")
         L.append("    int ch = -1;")
         L.append("    double sde_ch = 0.0, sde_all = 0.0;")
@@ -602,15 +621,19 @@ class Process:
         L.append("        }")
         L.append("    }")
         if mode == "jamps":
+            # all reads first (one wait), then the stores
+            L.append("    R jo[2 * NC];")
+            L.append("#pragma unroll")
+            L.append("    for (int s = 0; s < NC; ++s) {")
+            L.append("        jo[2 * s] = JGET(s, 0);")
+            L.append("        jo[2 * s + 1] = JGET(s, 1);")
+            L.append("    }")
             L.append("    if (e < n_evt) {")
             L.append("        R* o = jamp + (int64_t)h * (2 * NC) * ld + e;")
             L.append("#pragma unroll")
-            L.append("        for (int s = 0; s < NC; ++s) {")
-            L.append("            o[(2 * s) * ld] = JGET(s, 0);")
-            L.append("            o[(2 * s + 1) * ld] = JGET(s, 1);")
-            L.append("        }")
+            L.append("        for (int s = 0; s < 2 * NC; ++s) o[s * ld] = jo[s];")
             L.append("    }")
-        for m in ("PM", "JADD", "JGET", "JZERO", "JFLUSH", "SDEACC"):
+        for m in ("PM", "JADD", "JGET", "JZERO", "JTAKE", "JLAST", "JPUT", "SDEACC"):
             L.append(f"#undef {m}")
         L.append("}")
         return L
@@ -655,11 +678,13 @@ NOT_EMITTED = set()
 _PM = re.compile(r"PM\((\d+)\)")
 
 
-def _pipeline_momenta(lines, marks):
+def _pipeline_momenta(lines, marks, puts=None):
     """Rewrite a diagram program so that the momenta of amplitude step s are read from LDS
     into registers (const P4 m<s>_<i>) at one point: before the amplitude of step s-1
     (step 0: at its start).  marks[s] = (first node line, amplitude line, first jamp-update
-    line) of step s, indices into lines."""
+    line) of step s, indices into lines.  puts[s] (window programs): the partial-slot stores
+    of the slots step s evicted, placed after the amplitude of step s+1 (the caller places
+    those of the last step)."""
     out = []
     used = []
     for s, (a, b, c) in enumerate(marks):
@@ -667,7 +692,10 @@ def _pipeline_momenta(lines, marks):
         used.append(ks)
 
     def decl(s):
-        return [f"    const P4 m{s}_{k} = PM({k});" for k in used[s]]
+        return [f"    P4 m{s}_{k} = PM({k});" for k in used[s]]
+
+    def pin(s):
+        return [f"    pin_p4<R>(m{s}_{k});" for k in used[s]] if PIN_MOMENTA else []
 
     def sub(s, ln):
         return _PM.sub(lambda m: f"m{s}_{m.group(1)}", ln)
@@ -677,10 +705,13 @@ def _pipeline_momenta(lines, marks):
         out += lines[pos:a]                      # jamp updates of step s-1 (or preamble)
         if s == 0:
             out += decl(0)
+        out += pin(s)
         out += [sub(s, ln) for ln in lines[a:b]]   # nodes of step s
         if s + 1 < len(marks):
             out += decl(s + 1)                   # next step's reads, ahead of this step's atomics
         out += [sub(s, ln) for ln in lines[b:c]]   # amplitude (+ channel weight) of step s
+        if puts and s > 0:
+            out += puts[s - 1]
         pos = c
     out += lines[pos:]
     return out

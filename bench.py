@@ -58,14 +58,17 @@ def timed_steps(proc, x, steps, warmup, torch):
 
 def kernel_source_hash(process):
     """hash of the sources that define the amplitude kernel of `process` and its launch (the
-    helper header and the generated file up to the process descriptor)"""
+    helper headers and the generated file up to the process descriptor)"""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2210_11122_amd", "csrc")
     h = hashlib.sha256()
-    with open(os.path.join(csrc, "helas.hpp"), "rb") as fh:
-        h.update(fh.read())
     with open(os.path.join(csrc, "generated", f"proc_{process}.hip"), "rb") as fh:
-        h.update(fh.read().split(b"const ProcessDesc* process_")[0])
+        gen = fh.read().split(b"const ProcessDesc* process_")[0]
+    heads = ["helas.hpp"] + (["colorsum.hpp"] if b'#include "../colorsum.hpp"' in gen else [])
+    for name in heads:
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(fh.read())
+    h.update(gen)
     return h.hexdigest()[:16]
 
 
@@ -204,10 +207,14 @@ def main():
     lanes = n_evt * info["n_good_hel"]
     flops_amp_step = info["flops_amp_lane"] * lanes
     flops_cs_step = info["flops_colour_lane"] * lanes
+    fused = bool(info["fused_colour"])
+    # with the fused colour sum the amplitude kernel also does the colour contraction
+    flops_kernel_step = flops_amp_step + (flops_cs_step if fused else 0.0)
     amp_launches_per_step = n_amp / args.steps
-    achieved_tflops = flops_amp_step * args.steps / (ms_amp / 1e3) / 1e12
-    log(f"fp64: {ms64:.3f} ms/step, {mes64:.4g} MEs/s; amplitude kernel {ms_amp / args.steps:.3f} ms/step "
-        f"({achieved_tflops:.2f} TFLOP/s), colour sum {ms_cs / args.steps:.3f} ms/step")
+    achieved_tflops = flops_kernel_step * args.steps / (ms_amp / 1e3) / 1e12
+    log(f"fp64: {ms64:.3f} ms/step, {mes64:.4g} MEs/s; amplitude kernel{' (+ colour sum)' if fused else ''} "
+        f"{ms_amp / args.steps:.3f} ms/step ({achieved_tflops:.2f} TFLOP/s), "
+        f"{'helicity sum' if fused else 'colour sum'} {ms_cs / args.steps:.3f} ms/step")
 
     result = {
         "metric": "matrix elements/sec at 1 GPU (FP64; mixed precision at its stated rel. err)",
@@ -228,22 +235,24 @@ def main():
         "latency_ms": {"p50": quantile(lat64, 0.5), "p99": quantile(lat64, 0.99), "unit": "ms per me_sigma call"},
         "roofline": {
             "bound": "alu",
-            "kernel": "amplitude kernel (FP64 VALU)",
+            "kernel": ("amplitude kernel with the colour sum (FP64 VALU, FP64 MFMA)" if fused
+                       else "amplitude kernel (FP64 VALU)"),
             "achieved": achieved_tflops,
             "peak": FP64_VALU_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tflops / FP64_VALU_PEAK_TFLOPS,
             "traffic": None,  # filled below from the committed counter profile
-            "flops_per_launch": flops_amp_step / max(amp_launches_per_step, 1),
+            "flops_per_launch": flops_kernel_step / max(amp_launches_per_step, 1),
             "avg_launch_ms": ms_amp / max(n_amp, 1),
             "launches_per_step": amp_launches_per_step,
         },
-        "colour_sum": {
+        "colour_sum": ({"fused_into_amplitude_kernel": True, "helicity_sum_ms_per_step": ms_cs / args.steps}
+                       if fused else {
             "bound": "mfma",
             "achieved": flops_cs_step * args.steps / (ms_cs / 1e3) / 1e12 if ms_cs > 0 else None,
             "peak": MFMA_F64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "ms_per_step": ms_cs / args.steps,
-        },
+        }),
     }
 
     tr = measured_traffic(name)

@@ -135,6 +135,8 @@ typedef struct {
     int n_order;               /* entries per colour flow in me_colour_flows */
     int helicity_groups;       /* colour-sum launches split the good helicities into this many groups */
     int lines_per_diagram;     /* entries per diagram in me_diagrams */
+    int fused_colour;          /* 1: me_sigma / me_sigma_alphas contract the colour matrix inside the
+                                  amplitude kernel (FP64, processes whose jamps stay in LDS) */
 } me_info_t;
 
 int me_info(const me_handle *h, me_info_t *out);
@@ -150,10 +152,24 @@ int me_helicity_ratios(const me_handle *h, double *out);
 /* Launch timing, for measurement: with enable != 0, every later me_sigma call records a
  * HIP event pair around each kernel launch on its stream.  Each call returns (and clears)
  * what was recorded since the previous call: total milliseconds and launch counts of the
- * amplitude kernel and of the colour-sum kernel (it waits for those events).  Any pointer
- * may be NULL.  Not for use while another thread calls me_sigma on the same handle. */
+ * amplitude kernel and of the colour-sum kernel (it waits for those events).  With the
+ * fused colour sum (me_info_t.fused_colour) the amplitude figures include the colour
+ * contraction and the colour-sum figures are those of the helicity-sum kernel.  Any
+ * pointer may be NULL.  Not for use while another thread calls me_sigma on the same handle. */
 int me_profile(me_handle *h, int enable, double *ms_amp, double *ms_colour, int64_t *n_amp,
                int64_t *n_colour);
+
+/* Options of a handle, set between calls (not while work of the handle is being enqueued).
+ * ME_OPT_FUSED_COLOUR (default 1): for the plain FP64 |M|^2 of a process whose amplitude
+ * kernel keeps all jamps in LDS (gg_ttgg), the kernel contracts them with the colour matrix
+ * itself (the same matrix-core tiles, sums and order as the separate colour-sum kernel, so
+ * each helicity's |M_h|^2 is bitwise the same) and writes one FP64 value per (event,
+ * helicity) instead of the jamps; a second kernel sums the helicities in a fixed order.
+ * 0: always the separate colour-sum kernel; for such processes its FP64 form adds the
+ * helicities one by one in the same order, so both settings give bitwise the same result.
+ * ME_EINVAL for an unknown option or a value other than 0 or 1. */
+enum { ME_OPT_FUSED_COLOUR = 1 };
+int me_set_option(me_handle *h, int option, int value);
 
 const char *me_last_error(void); /* thread-local; valid until the thread's next call */
 

@@ -11,6 +11,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libme.so")
 
 ME_FP64, ME_MIXED_FP16, ME_MIXED_BF16 = 0, 1, 2
+ME_OPT_FUSED_COLOUR = 1
 PRECISIONS = {"fp64": ME_FP64, "mixed_fp16": ME_MIXED_FP16, "mixed_bf16": ME_MIXED_BF16}
 ME_OK = 0
 PROCESSES = ["ee_mumu", "gg_tt", "gg_ttg", "gg_ttgg", "gg_ttggg", "gg_gg", "ee_mumu_z"]
@@ -28,7 +29,7 @@ class MeInfo(ctypes.Structure):
                 ("n_partial_slots", ctypes.c_int), ("flops_colour_lane", ctypes.c_double),
                 ("bytes_resident", ctypes.c_int64), ("bytes_per_event_scratch", ctypes.c_int64),
                 ("chunk_events", ctypes.c_int64), ("n_order", ctypes.c_int), ("helicity_groups", ctypes.c_int),
-                ("lines_per_diagram", ctypes.c_int)]
+                ("lines_per_diagram", ctypes.c_int), ("fused_colour", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -36,7 +37,7 @@ class MeInfo(ctypes.Structure):
 
 EXPORTS = ["me_create", "me_destroy", "me_info", "me_last_error", "rambo_momenta", "me_sigma",
            "me_sigma_hel", "me_sigma_select", "me_sigma_alphas", "me_sigma_channel", "me_diagrams", "me_colour_flows", "me_good_helicities", "me_helicity_ratios",
-           "me_profile"]
+           "me_profile", "me_set_option"]
 
 _lib = None
 
@@ -66,6 +67,7 @@ def load():
     L.me_good_helicities.argtypes = [vp, ctypes.POINTER(ctypes.c_byte)]
     L.me_helicity_ratios.argtypes = [vp, D]
     L.me_profile.argtypes = [vp, ctypes.c_int, D, D, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    L.me_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     _lib = L
     return L
 
@@ -218,6 +220,11 @@ class Process:
         _check(load().me_profile(self._h, int(enable), ctypes.byref(a), ctypes.byref(c), ctypes.byref(na),
                                  ctypes.byref(nc)), "me_profile")
         return a.value, c.value, na.value, nc.value
+
+    def set_fused_colour(self, enable):
+        """colour sum inside the FP64 amplitude kernel where the process has one (default on)"""
+        _check(load().me_set_option(self._h, ME_OPT_FUSED_COLOUR, int(bool(enable))), "me_set_option")
+        self.info = self._info()
 
     def good_helicities(self):
         n = self.info["n_good_hel"]

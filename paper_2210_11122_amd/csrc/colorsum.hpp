@@ -154,6 +154,49 @@ __global__ __launch_bounds__(256) void colour_sum_f64(const JT* __restrict__ J, 
     if (g == 0 && valid) cs_store(me, e, n_evt, scale_avg, out, part);
 }
 
+// The same contraction inside an amplitude kernel whose wave (64 events of one helicity) holds
+// its FP64 jamps in LDS, Jl[(2c + re/im) * 64 + event]: for each of the four 16-event tiles the
+// lanes load the B operands from the other lanes' slots and form, per event, the same products
+// and sums in the same order as colour_sum_f64 (so each |M_h|^2 is bitwise the same).  Returns
+// this lane's event's D * |M_h|^2.  The caller must have completed all jamp updates of the wave
+// (a barrier) before the call.
+template <int NC>
+__device__ __forceinline__ double colour_sum_lds(const double* Jl, const double* __restrict__ aop, int lane)
+{
+    constexpr int MT = (NC + 15) / 16, KT = (NC + 3) / 4, NT = cs64_tiles(NC);
+    const int i = lane & 15, g = lane >> 4;
+    double A[NT];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) A[q] = aop[q * 64 + lane];
+    double mine = 0.0;
+#pragma unroll 1
+    for (int j = 0; j < 4; ++j) {  // events 16 j .. 16 j + 15
+        double part = 0.0;
+#pragma unroll
+        for (int ri = 0; ri < 2; ++ri) {
+            double b[KT];
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt) {
+                const int c = 4 * kt + g;
+                b[kt] = (c < NC) ? Jl[(2 * c + ri) * 64 + 16 * j + i] : 0.0;
+            }
+            int q = 0;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                v4d d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int kt = 4 * mt; kt < KT; ++kt, ++q) d = __builtin_amdgcn_mfma_f64_16x16x4f64(A[q], b[kt], d, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (4 * mt + r < KT) part += b[4 * mt + r] * d[r];
+            }
+        }
+        part = sum_lane_groups(part);
+        if (g == j) mine = part;  // lane 16 g + i is event 16 g + i
+    }
+    return mine;
+}
+
 // 16-bit element types of the mixed colour sum
 struct Fp16Terms {
     typedef _Float16 elem;
@@ -272,7 +315,7 @@ __global__ __launch_bounds__(256) void colour_sum_h16(const float* __restrict__ 
 }
 
 // out[e] = scale * sum over helicity groups of part[group][e], groups in order
-__global__ __launch_bounds__(256) void hel_reduce(const double* __restrict__ part, int groups, int64_t n_evt,
+static __global__ __launch_bounds__(256) void hel_reduce(const double* __restrict__ part, int groups, int64_t n_evt,
                                                   double scale, double* __restrict__ out)
 {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;

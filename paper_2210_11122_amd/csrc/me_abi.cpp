@@ -83,6 +83,7 @@ struct me_handle {
     __bf16* d_aopb_lo = nullptr;   // BF16 A_lo (exact remainder of numerators BF16 cannot hold)
     uint64_t lo_mask_b16 = 0;      // tiles with a non-zero A_lo
     int groups = 1, hel_per_group = 1;  // helicity split of the colour sum
+    bool fuse_colour = true;            // use the amplitude kernel's own colour sum where it has one
     size_t jamp_bytes_per_event = 0;
     size_t bytes_resident = 0;
     int64_t chunk = 0;
@@ -286,6 +287,9 @@ int run_chunks(me_handle* h, int precision, const signed char* hel, int n_good, 
 {
     const me::ProcessDesc* P = h->P;
     const bool fp64 = precision == ME_FP64;
+    // the colour sum inside the amplitude kernel: plain FP64 |M|^2 only (the selection, the
+    // per-helicity output and the channel weights read the jamps)
+    const bool fused = fp64 && P->fused_colour && h->fuse_colour && !sel && !out_hel && !chan;
     void* jamp = scratch;
     double* part = reinterpret_cast<double*>(static_cast<char*>(scratch) + (size_t)chunk * jamp_bytes_per_event);
     for (int64_t c0 = 0; c0 < n; c0 += chunk) {
@@ -294,15 +298,32 @@ int run_chunks(me_handle* h, int precision, const signed char* hel, int n_good, 
         const double* m = mom + c0 * P->npar * 4;
         TimedLaunch ta(h, st, 0, timed);
         const int* ch = chan ? chan + c0 : nullptr;
-        hipError_t e = fp64 ? P->launch_f64(m, nc, ld, hel, n_good, h->mt, h->g, static_cast<double*>(jamp), ch, sde, st)
-                            : P->launch_f32(m, nc, ld, hel, n_good, h->mt, h->g, static_cast<float*>(jamp), ch, sde, st);
-        ta.done();
-        if (e != hipSuccess) return fail(ME_EHIP, std::string("amplitude kernel: ") + hipGetErrorString(e));
-        TimedLaunch tc(h, st, 1, timed);
-        double* oh = sel ? sel->hel_me : (out_hel ? out_hel + c0 * n_good : nullptr);
-        e = colour_sum(h, precision, jamp, ld, n_good, hel_per_group, groups, nc, out + c0, oh, part, st);
-        tc.done();
-        if (e != hipSuccess) return fail(ME_EHIP, std::string("colour-sum kernel: ") + hipGetErrorString(e));
+        hipError_t e;
+        if (fused) {
+            // the amplitude kernel ends with the colour sum: D |M_h|^2 per (helicity, event) in the
+            // jamp scratch, then the helicity sum in a fixed order
+            e = P->launch_f64(m, nc, ld, hel, n_good, h->mt, h->g, static_cast<double*>(jamp), nullptr, nullptr,
+                              h->d_aop64, st);
+            ta.done();
+            if (e != hipSuccess) return fail(ME_EHIP, std::string("amplitude kernel: ") + hipGetErrorString(e));
+            TimedLaunch tc(h, st, 1, timed);
+            hipLaunchKernelGGL(me::hel_reduce, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st,
+                               static_cast<const double*>(jamp), n_good, nc,
+                               1.0 / ((double)P->colour_den * P->avg), out + c0);
+            e = hipGetLastError();
+            tc.done();
+            if (e != hipSuccess) return fail(ME_EHIP, std::string("helicity-sum kernel: ") + hipGetErrorString(e));
+        } else {
+            e = fp64 ? P->launch_f64(m, nc, ld, hel, n_good, h->mt, h->g, static_cast<double*>(jamp), ch, sde, nullptr, st)
+                     : P->launch_f32(m, nc, ld, hel, n_good, h->mt, h->g, static_cast<float*>(jamp), ch, sde, nullptr, st);
+            ta.done();
+            if (e != hipSuccess) return fail(ME_EHIP, std::string("amplitude kernel: ") + hipGetErrorString(e));
+            TimedLaunch tc(h, st, 1, timed);
+            double* oh = sel ? sel->hel_me : (out_hel ? out_hel + c0 * n_good : nullptr);
+            e = colour_sum(h, precision, jamp, ld, n_good, hel_per_group, groups, nc, out + c0, oh, part, st);
+            tc.done();
+            if (e != hipSuccess) return fail(ME_EHIP, std::string("colour-sum kernel: ") + hipGetErrorString(e));
+        }
         if (chan) {
             hipLaunchKernelGGL(sde_apply, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, out + c0, sde, ch,
                                n_good, ld, nc);
@@ -538,11 +559,27 @@ me_handle* me_create(const char* process, const double* masses, int n_masses, co
     h->chunk = std::max<int64_t>(64, chunk);
     // the helicity split is fixed per handle, so an event's result does not depend on the batch
     helicity_groups(P, h->n_good, h->chunk, &h->groups, &h->hel_per_group);
+    if (precision == ME_FP64 && P->fused_colour) {
+        // one helicity per group: the separate colour sum then adds the same per-helicity values
+        // in the same order as the fused kernel's helicity sum, so every FP64 path (and either
+        // setting of ME_OPT_FUSED_COLOUR) gives bitwise the same |M|^2
+        h->hel_per_group = 1;
+        h->groups = h->n_good;
+    }
     h->bytes_per_event = h->jamp_bytes_per_event + (h->groups > 1 ? h->groups * sizeof(double) : 0);
     return h;
 }
 
 void me_destroy(me_handle* h) { free_handle(h); }
+
+int me_set_option(me_handle* h, int option, int value)
+{
+    if (!h) return fail(ME_EINVAL, "handle is NULL");
+    if (option != ME_OPT_FUSED_COLOUR) return fail(ME_EINVAL, "unknown option");
+    if (value != 0 && value != 1) return fail(ME_EINVAL, "option value must be 0 or 1");
+    h->fuse_colour = value != 0;
+    return ME_OK;
+}
 
 int me_info(const me_handle* h, me_info_t* out)
 {
@@ -567,6 +604,7 @@ int me_info(const me_handle* h, me_info_t* out)
     out->n_order = P->n_order;
     out->helicity_groups = h->groups;
     out->lines_per_diagram = P->lines_per_diagram;
+    out->fused_colour = (h->precision == ME_FP64 && P->fused_colour && h->fuse_colour) ? 1 : 0;
     return ME_OK;
 }
 

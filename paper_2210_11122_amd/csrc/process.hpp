@@ -7,12 +7,14 @@ namespace me {
 
 // chan == nullptr: plain kernels; otherwise chan[n_evt] channel ids and sde[n_good][2][ld] the
 // per-lane single-diagram sums (channel, all)
+// aop (FP64 only, processes with fused_colour): the colour-matrix operands of colour_sum_f64;
+// when given, the kernel writes D |M_h|^2 to jamp[h * n_evt + event] instead of the jamps
 typedef hipError_t (*amp_launch_f64)(const double* mom, int64_t n_evt, int64_t ld, const signed char* hel,
                                      int n_good, double mt, double g, double* jamp, const int* chan, double* sde,
-                                     hipStream_t st);
+                                     const double* aop, hipStream_t st);
 typedef hipError_t (*amp_launch_f32)(const double* mom, int64_t n_evt, int64_t ld, const signed char* hel,
                                      int n_good, double mt, double g, float* jamp, const int* chan, double* sde,
-                                     hipStream_t st);
+                                     const double* aop, hipStream_t st);  // aop: must be null
 
 struct ProcessDesc {
     const char* name;
@@ -35,6 +37,7 @@ struct ProcessDesc {
     const int* diagram_lines;  // n_diagrams x lines_per_diagram internal-line masks (0-padded)
     int lines_per_diagram;
     int sde_supported;         // single-diagram channel weights available
+    int fused_colour;          // the FP64 amplitude kernel can do the colour sum itself (aop)
     amp_launch_f64 launch_f64;
     amp_launch_f32 launch_f32;
 };

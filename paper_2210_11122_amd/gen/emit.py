@@ -440,8 +440,13 @@ class Process:
             L.append(f"// {len(kernels)} segment kernels, {self.segments[1]}-slot LDS jamp window, "
                      f"{self.nslot} partial jamp slots; executed flops per lane {self.flops_exec} "
                      f"(algorithmic {fl}).")
+        # the FP64 kernel can finish with the colour sum when its jamps are in LDS and complete
+        fused = bool(jamps_in_lds) and not self.segments and self.kind != "ee"
+        self.fused_colour = fused
         L.append('#include "../helas.hpp"')
         L.append('#include "../process.hpp"')
+        if fused:
+            L.append('#include "../colorsum.hpp"')
         L.append("namespace me {")
         L.append(f"namespace proc_{nm} {{")
         L.append(f"constexpr int NPAR = {self.npar};")
@@ -477,7 +482,7 @@ class Process:
                              f"int, double, double, {R}*, const int*, double*, hipStream_t, int64_t);")
         else:
             for kname, body, nwin, mode in kernels:
-                L += self._kernel_text(kname, body, nwin, mode, jamps_in_lds, jamp_mode)
+                L += self._kernel_text(kname, body, nwin, mode, jamps_in_lds, jamp_mode, fused=fused)
         L.append("")
         L.append(f"static const int colour_num[NC * NC] = {{{cn}}};")
         L.append(f"static const int final_massive[NPAR - 2] = {{{masses}}};")
@@ -492,8 +497,13 @@ class Process:
             L += self._reduce_text()
         L.append("template <class R>")
         L.append("static hipError_t launch(const double* mom, int64_t n_evt, int64_t ld, const signed char* hel, "
-                 "int n_good, double mt, double gs, R* jamp, const int* chan, double* sde, hipStream_t st)")
+                 "int n_good, double mt, double gs, R* jamp, const int* chan, double* sde, const double* aop, "
+                 "hipStream_t st)")
         L.append("{")
+        if not fused:
+            L.append("    if (aop) return hipErrorInvalidValue;  // no fused colour sum for this process")
+        else:
+            L.append("    if (aop && (sizeof(R) != 8 || chan)) return hipErrorInvalidValue;")
         L.append("    int64_t blocks = ((n_evt + 63) / 64) * n_good;")
         L.append("    if (blocks == 0) return hipSuccess;")
         for kname, _, _, _ in kernels:
@@ -507,11 +517,13 @@ class Process:
                 L.append("    }")
             else:
                 L.append("    if (chan)")
+                tail = ", nullptr" if fused else ""
                 L.append(f"        hipLaunchKernelGGL(({kname}<R, true>), dim3((unsigned)blocks), dim3(64), 0, st, mom, n_evt, "
-                         "ld, hel, n_good, mt, gs, jamp, chan, sde);")
+                         f"ld, hel, n_good, mt, gs, jamp, chan, sde{tail});")
                 L.append("    else")
+                tail = ", aop" if fused else ""
                 L.append(f"        hipLaunchKernelGGL(({kname}<R, false>), dim3((unsigned)blocks), dim3(64), 0, st, mom, n_evt, "
-                         "ld, hel, n_good, mt, gs, jamp, nullptr, nullptr);")
+                         f"ld, hel, n_good, mt, gs, jamp, nullptr, nullptr{tail});")
         if self.segments:
             L.append("    hipLaunchKernelGGL(reduce_kernel<R>, dim3((unsigned)((n_evt + 255) / 256), (unsigned)n_good), "
                      "dim3(256), 0, st, jamp, ld, n_good, n_evt);")
@@ -526,7 +538,7 @@ class Process:
         L.append(f"        proc_{nm}::colour_num, {self.cden}, proc_{nm}::final_massive, proc_{nm}::orderings, "
                  f"{n_order},")
         L.append(f"        {self.n_diagrams}, {self.n_amplitudes}, {fl}.0, {self.flops_exec}.0, proc_{nm}::NSLOT,")
-        L.append(f"        proc_{nm}::diagram_lines, {nlines}, {0 if self.lines is None else 1},")
+        L.append(f"        proc_{nm}::diagram_lines, {nlines}, {0 if self.lines is None else 1}, {1 if fused else 0},")
         L.append(f"        proc_{nm}::launch<double>, proc_{nm}::launch<float>,")
         L.append("    };")
         L.append("    return &d;")
@@ -534,7 +546,7 @@ class Process:
         L.append("}  // namespace me")
         return "\n".join(L) + "\n"
 
-    def _kernel_text(self, kname, body, nwin, mode, jamps_in_lds, jamp_mode, first=True):
+    def _kernel_text(self, kname, body, nwin, mode, jamps_in_lds, jamp_mode, first=True, fused=False):
         """one amplitude kernel: momenta staging, helicity signs, jamp storage, body, output.
         mode 'jamps': the NC jamps are written at the end, layout [h][2c + re/im][column];
         mode 'slots': the body evicts window slots to partial slots (JTAKE, later JPUT), layout
@@ -549,7 +561,8 @@ class Process:
         bounds = "64" if (w64, w32) == (1, 1) else f"64, (sizeof(R) == 8 ? {w64} : {w32})"
         L.append(f"__global__ __launch_bounds__({bounds}) void {kname}(const double* __restrict__ mom, int64_t n_evt, "
                  "int64_t ld, const signed char* __restrict__ hel, int n_good, double mt, double gs, "
-                 "R* __restrict__ jamp, const int* __restrict__ chan, double* __restrict__ sde)")
+                 "R* __restrict__ jamp, const int* __restrict__ chan, double* __restrict__ sde"
+                 + (", const double* __restrict__ aop)" if fused else ")"))
         L.append("{")
         L.append("    __shared__ double lds[4 * NPAR * 64];")
         L.append("    const int lane = threadIdx.x;")
@@ -621,6 +634,15 @@ class Process:
         L.append("        }")
         L.append("    }")
         if mode == "jamps":
+            if fused:
+                L.append("    if constexpr (sizeof(R) == 8) {")
+                L.append("        if (aop) {  // colour sum here: D |M_h|^2 of this lane's event, to jamp[h][event]")
+                L.append("            __syncthreads();  // every jamp update of the wave has completed")
+                L.append("            const double me_h = colour_sum_lds<NC>(Jl, aop, lane);")
+                L.append("            if (e < n_evt) jamp[(int64_t)h * n_evt + e] = me_h;")
+                L.append("            return;")
+                L.append("        }")
+                L.append("    }")
             # all reads first (one wait), then the stores
             L.append("    R jo[2 * NC];")
             L.append("#pragma unroll")

@@ -34,3 +34,13 @@ def test_library_exports_every_declared_symbol():
 def test_binding_export_list_matches_header():
     from paper_2210_11122_amd import binding
     assert sorted(binding.EXPORTS) == declared_functions()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libme.so not built")
+def test_host_only_argument_checks():
+    """entry points that reject a NULL handle before any device call"""
+    lib = ctypes.CDLL(LIB)
+    lib.me_set_option.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
+    lib.me_last_error.restype = ctypes.c_char_p
+    assert lib.me_set_option(None, 1, 1) == -1
+    assert b"NULL" in lib.me_last_error()

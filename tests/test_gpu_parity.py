@@ -151,6 +151,28 @@ def test_result_independent_of_batch(name, precision):
     assert np.array_equal(full[:37], head) and np.array_equal(full[n - 101:], tail)
 
 
+def test_fused_colour_sum_equals_separate_kernel():
+    """gg_ttgg FP64: the colour sum inside the amplitude kernel (the default) and the separate
+    colour-sum kernel give bitwise the same |M|^2 (same per-helicity products, helicities added
+    one by one in the same order), over two launches with a ragged tail"""
+    import ctypes
+    from paper_2210_11122_amd import binding
+    name = "gg_ttgg"
+    proc = make_process(name)
+    assert proc.info["fused_colour"] == 1 and proc.info["helicity_groups"] == proc.info["n_good_hel"]
+    n = proc.info["chunk_events"] + 777
+    print(f"case fused colour sum {name} n={n}", flush=True)
+    x = proc.rambo(5, W.sqrt_s(name), n)
+    fused = proc.sigma(x).cpu().numpy()
+    proc.set_fused_colour(False)
+    assert proc.info["fused_colour"] == 0
+    sep = proc.sigma(x).cpu().numpy()
+    assert np.array_equal(fused, sep) and np.all(fused > 0)
+    L = binding.load()
+    assert L.me_set_option(proc._h, 99, 1) == -1 and "unknown option" in binding.last_error()
+    assert L.me_set_option(proc._h, binding.ME_OPT_FUSED_COLOUR, 2) == -1
+
+
 def test_large_batch_sampled_parity():
     """gg_ttgg at the full configuration size (2^19 events, several chunks, the bench's launch
     configuration): sampled events against the oracle one by one"""
@@ -218,3 +240,5 @@ def test_info_counts():
                              ("gg_ttgg", 123, 24, 64), ("gg_ttggg", 1240, 120, 128)]:
         i = make_process(name).info
         assert (i["n_diagrams"], i["n_colors"], i["n_hel"]) == (nd, nc, nh)
+        assert i["fused_colour"] == (1 if name == "gg_ttgg" else 0)
+    assert make_process("gg_ttgg", "mixed_fp16").info["fused_colour"] == 0

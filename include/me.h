@@ -136,7 +136,7 @@ typedef struct {
     int helicity_groups;       /* colour-sum launches split the good helicities into this many groups */
     int lines_per_diagram;     /* entries per diagram in me_diagrams */
     int fused_colour;          /* 1: me_sigma / me_sigma_alphas contract the colour matrix inside the
-                                  amplitude kernel (FP64, processes whose jamps stay in LDS) */
+                                  amplitude kernel (every process but gg_ttggg) */
 } me_info_t;
 
 int me_info(const me_handle *h, me_info_t *out);
@@ -160,13 +160,15 @@ int me_profile(me_handle *h, int enable, double *ms_amp, double *ms_colour, int6
                int64_t *n_colour);
 
 /* Options of a handle, set between calls (not while work of the handle is being enqueued).
- * ME_OPT_FUSED_COLOUR (default 1): for the plain FP64 |M|^2 of a process whose amplitude
- * kernel keeps all jamps in LDS (gg_ttgg), the kernel contracts them with the colour matrix
- * itself (the same matrix-core tiles, sums and order as the separate colour-sum kernel, so
- * each helicity's |M_h|^2 is bitwise the same) and writes one FP64 value per (event,
- * helicity) instead of the jamps; a second kernel sums the helicities in a fixed order.
- * 0: always the separate colour-sum kernel; for such processes its FP64 form adds the
- * helicities one by one in the same order, so both settings give bitwise the same result.
+ * ME_OPT_FUSED_COLOUR (default 1): for the plain |M|^2 (me_sigma, me_sigma_alphas) of a
+ * process whose amplitude kernel ends holding all jamps of its lanes (every process but
+ * gg_ttggg, whose jamps come out of a window of partial sums), in every precision, the
+ * kernel contracts them with the colour matrix itself (the same matrix-core tiles, operand
+ * splits, sums and order as the separate colour-sum kernel of that precision, so each
+ * helicity's |M_h|^2 is bitwise the same) and writes one FP64 value per (event, helicity)
+ * instead of the jamps; a second kernel sums the helicities in the separate kernel's groups
+ * and order.  0: always the separate colour-sum kernel.  Both settings, and the calls that
+ * need the jamps (me_sigma_hel, me_sigma_select), give bitwise the same |M|^2.
  * ME_EINVAL for an unknown option or a value other than 0 or 1. */
 enum { ME_OPT_FUSED_COLOUR = 1 };
 int me_set_option(me_handle *h, int option, int value);

@@ -94,6 +94,44 @@ __device__ __forceinline__ void cs_store(double me, int64_t e, int64_t n_evt, do
         part[(int64_t)blockIdx.y * n_evt + e] = me;
 }
 
+// One (16-event tile, helicity) column block of the FP64 form: returns this lane's share of
+// D * |M_h|^2 for event column i (the four lane groups' shares add up to it).  load(c, ri) gives
+// the jamp of colour c (re/im) of this lane's column.  A: the tile operands in registers when
+// AREG, else read from aop.
+template <int NC, bool AREG, class Load>
+__device__ __forceinline__ double cs64_column(const Load& load, const double* A, const double* aop, int lane)
+{
+    constexpr int MT = (NC + 15) / 16, KT = (NC + 3) / 4;
+    const int g = lane >> 4;
+    double part_h = 0.0;
+    // the real/imaginary loop stays rolled for the large matrices (register pressure)
+#pragma unroll (NC > 24 ? 1 : 2)
+    for (int ri = 0; ri < 2; ++ri) {
+        // this lane's B elements: colours c = 4 kt + g, which are also its D rows
+        double b[KT];
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) {
+            const int c = 4 * kt + g;
+            b[kt] = (c < NC) ? (double)load(c, ri) : 0.0;
+        }
+        int q = 0;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const double* ap = opaque(aop);
+            v4d d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kt = 4 * mt; kt < KT; ++kt, ++q) {
+                const double a = AREG ? A[q] : ap[q * 64 + lane];
+                d = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[kt], d, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (4 * mt + r < KT) part_h += b[4 * mt + r] * d[r];
+        }
+    }
+    return part_h;
+}
+
 // A operands, per lane, in the kernel's tile order (mt ascending, then kt >= 4 mt):
 // aop[q * 64 + l] = A[16 mt + l % 16][4 kt + l / 16].  JT: the jamps' storage type (float for the
 // mixed forms' small colour matrices, which a 16x16x32 tile would mostly pad with zeros).
@@ -104,7 +142,7 @@ __global__ __launch_bounds__(256) void colour_sum_f64(const JT* __restrict__ J, 
                                                       double scale_avg, double* __restrict__ out,
                                                       double* __restrict__ out_hel, double* __restrict__ part)
 {
-    constexpr int MT = (NC + 15) / 16, KT = (NC + 3) / 4, NT = cs64_tiles(NC);
+    constexpr int NT = cs64_tiles(NC);
     constexpr bool AREG = NT <= 24;
     const int lane = threadIdx.x & 63;
     const int64_t e0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
@@ -122,79 +160,12 @@ __global__ __launch_bounds__(256) void colour_sum_f64(const JT* __restrict__ J, 
     double me = 0.0;
     for (int h = h0; h < h1; ++h) {
         const JT* Jh = J + (int64_t)h * (2 * NC) * ld;
-        double part_h = 0.0;
-#pragma unroll 1
-        for (int ri = 0; ri < 2; ++ri) {
-            // this lane's B elements: colours c = 4 kt + g, which are also its D rows
-            double b[KT];
-#pragma unroll
-            for (int kt = 0; kt < KT; ++kt) {
-                const int c = 4 * kt + g;
-                b[kt] = (c < NC) ? (double)Jh[(int64_t)(2 * c + ri) * ld + ec] : 0.0;
-            }
-            int q = 0;
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                const double* ap = opaque(aop);
-                v4d d = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int kt = 4 * mt; kt < KT; ++kt, ++q) {
-                    const double a = AREG ? A[q] : ap[q * 64 + lane];
-                    d = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[kt], d, 0, 0, 0);
-                }
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (4 * mt + r < KT) part_h += b[4 * mt + r] * d[r];
-            }
-        }
-        part_h = sum_lane_groups(part_h);
+        const auto load = [&](int c, int ri) { return Jh[(int64_t)(2 * c + ri) * ld + ec]; };
+        double part_h = sum_lane_groups(cs64_column<NC, AREG>(load, A, aop, lane));
         if (out_hel && g == 0 && valid) out_hel[e * n_good + h] = part_h * scale_hel;
         me += part_h;
     }
     if (g == 0 && valid) cs_store(me, e, n_evt, scale_avg, out, part);
-}
-
-// The same contraction inside an amplitude kernel whose wave (64 events of one helicity) holds
-// its FP64 jamps in LDS, Jl[(2c + re/im) * 64 + event]: for each of the four 16-event tiles the
-// lanes load the B operands from the other lanes' slots and form, per event, the same products
-// and sums in the same order as colour_sum_f64 (so each |M_h|^2 is bitwise the same).  Returns
-// this lane's event's D * |M_h|^2.  The caller must have completed all jamp updates of the wave
-// (a barrier) before the call.
-template <int NC>
-__device__ __forceinline__ double colour_sum_lds(const double* Jl, const double* __restrict__ aop, int lane)
-{
-    constexpr int MT = (NC + 15) / 16, KT = (NC + 3) / 4, NT = cs64_tiles(NC);
-    const int i = lane & 15, g = lane >> 4;
-    double A[NT];
-#pragma unroll
-    for (int q = 0; q < NT; ++q) A[q] = aop[q * 64 + lane];
-    double mine = 0.0;
-#pragma unroll 1
-    for (int j = 0; j < 4; ++j) {  // events 16 j .. 16 j + 15
-        double part = 0.0;
-#pragma unroll
-        for (int ri = 0; ri < 2; ++ri) {
-            double b[KT];
-#pragma unroll
-            for (int kt = 0; kt < KT; ++kt) {
-                const int c = 4 * kt + g;
-                b[kt] = (c < NC) ? Jl[(2 * c + ri) * 64 + 16 * j + i] : 0.0;
-            }
-            int q = 0;
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                v4d d = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int kt = 4 * mt; kt < KT; ++kt, ++q) d = __builtin_amdgcn_mfma_f64_16x16x4f64(A[q], b[kt], d, 0, 0, 0);
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (4 * mt + r < KT) part += b[4 * mt + r] * d[r];
-            }
-        }
-        part = sum_lane_groups(part);
-        if (g == j) mine = part;  // lane 16 g + i is event 16 g + i
-    }
-    return mine;
 }
 
 // 16-bit element types of the mixed colour sum
@@ -221,6 +192,75 @@ struct Bf16Terms {
     }
 };
 
+// One (16-event tile, helicity) column block of the mixed forms: this lane's share of
+// D * |M_h|^2 for event column i, from the FP32 jamps load(c, ri) of its column.
+template <int NC, class T, bool AREG, class Load>
+__device__ __forceinline__ double cs16_column(const Load& load, const typename T::vec* A,
+                                              const typename T::elem* aop, const typename T::elem* aop_lo,
+                                              uint64_t lo_mask, int lane)
+{
+    typedef typename T::vec vec;
+    typedef typename T::elem elem;
+    constexpr int MT = (NC + 15) / 16, KB = (MT + 1) / 2;
+    const int g = lane >> 4;
+    double part_h = 0.0;
+#pragma unroll 1
+    for (int ri = 0; ri < 2; ++ri) {
+        // x[kb][t]: colour 16 (2 kb + t / 4) + 4 g + t % 4 of column i
+        float x[KB][8];
+        float mx = 0.0f;
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int c = 16 * (2 * kb + t / 4) + 4 * g + t % 4;
+                const float v = (c < NC) ? (float)load(c, ri) : 0.0f;
+                x[kb][t] = v;
+                mx = fmaxf(mx, fabsf(v));
+            }
+        mx = max_lane_groups(mx);
+        // power-of-two scale: largest |J| of the column into [1/2, 1)
+        int ex = 0;
+        if (mx > 0.0f) frexpf(mx, &ex);
+        const float s = ldexpf(1.0f, -ex);
+        vec bh[KB], bl[KB];
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const float v = x[kb][t] * s;
+                const elem hi = T::round(v);
+                bh[kb][t] = hi;
+                bl[kb][t] = T::round((v - T::value(hi)) * T::LO);
+                x[kb][t] = v;
+            }
+        double acc = 0.0;  // the column dot product, in FP64 (colour sums can cancel)
+        int q = 0;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const elem* ap = opaque(aop);
+            const elem* ap_lo = opaque(aop_lo);
+            v4f dh = {0.f, 0.f, 0.f, 0.f}, dl = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = mt / 2; kb < KB; ++kb, ++q) {
+                const vec a = AREG ? A[q] : *reinterpret_cast<const vec*>(ap + (q * 64 + lane) * 8);
+                dh = T::mfma(a, bh[kb], dh);
+                dl = T::mfma(a, bl[kb], dl);
+                if ((lo_mask >> q) & 1) {
+                    const vec alo = *reinterpret_cast<const vec*>(ap_lo + (q * 64 + lane) * 8);
+                    dh = T::mfma(alo, bh[kb], dh);
+                }
+            }
+            // D rows 16 mt + 4 g + r are this lane's x[mt / 2][4 (mt % 2) + r]
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                acc += (double)x[mt / 2][4 * (mt % 2) + r] * ((double)dh[r] + (double)dl[r] * (1.0 / T::LO));
+        }
+        part_h += acc / ((double)s * (double)s);
+    }
+    return part_h;
+}
+
 // A operands, per lane, in the kernel's tile order (mt ascending, then kb >= mt / 2):
 // aop[(q * 64 + l) * 8 + t] = A[16 mt + l % 16][colour of k slot (kb, 8 (l / 16) + t)].
 // aop_lo (A_lo, same layout) is read for the tiles whose bit is set in lo_mask.
@@ -233,8 +273,7 @@ __global__ __launch_bounds__(256) void colour_sum_h16(const float* __restrict__ 
                                                       double* __restrict__ out_hel, double* __restrict__ part)
 {
     typedef typename T::vec vec;
-    typedef typename T::elem elem;
-    constexpr int MT = (NC + 15) / 16, KB = (MT + 1) / 2, NT = cs16_tiles(NC);
+    constexpr int NT = cs16_tiles(NC);
     constexpr bool AREG = NT <= 8;
     const int lane = threadIdx.x & 63;
     const int64_t e0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
@@ -252,66 +291,77 @@ __global__ __launch_bounds__(256) void colour_sum_h16(const float* __restrict__ 
     double me = 0.0;
     for (int h = h0; h < h1; ++h) {
         const float* Jh = J + (int64_t)h * (2 * NC) * ld;
-        double part_h = 0.0;
-#pragma unroll 1
-        for (int ri = 0; ri < 2; ++ri) {
-            // x[kb][t]: colour 16 (2 kb + t / 4) + 4 g + t % 4 of column i
-            float x[KB][8];
-            float mx = 0.0f;
-#pragma unroll
-            for (int kb = 0; kb < KB; ++kb)
-#pragma unroll
-                for (int t = 0; t < 8; ++t) {
-                    const int c = 16 * (2 * kb + t / 4) + 4 * g + t % 4;
-                    const float v = (c < NC) ? Jh[(int64_t)(2 * c + ri) * ld + ec] : 0.0f;
-                    x[kb][t] = v;
-                    mx = fmaxf(mx, fabsf(v));
-                }
-            mx = max_lane_groups(mx);
-            // power-of-two scale: largest |J| of the column into [1/2, 1)
-            int ex = 0;
-            if (mx > 0.0f) frexpf(mx, &ex);
-            const float s = ldexpf(1.0f, -ex);
-            vec bh[KB], bl[KB];
-#pragma unroll
-            for (int kb = 0; kb < KB; ++kb)
-#pragma unroll
-                for (int t = 0; t < 8; ++t) {
-                    const float v = x[kb][t] * s;
-                    const elem hi = T::round(v);
-                    bh[kb][t] = hi;
-                    bl[kb][t] = T::round((v - T::value(hi)) * T::LO);
-                    x[kb][t] = v;
-                }
-            double acc = 0.0;  // the column dot product, in FP64 (colour sums can cancel)
-            int q = 0;
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                const elem* ap = opaque(aop);
-                const elem* ap_lo = opaque(aop_lo);
-                v4f dh = {0.f, 0.f, 0.f, 0.f}, dl = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int kb = mt / 2; kb < KB; ++kb, ++q) {
-                    const vec a = AREG ? A[q] : *reinterpret_cast<const vec*>(ap + (q * 64 + lane) * 8);
-                    dh = T::mfma(a, bh[kb], dh);
-                    dl = T::mfma(a, bl[kb], dl);
-                    if ((lo_mask >> q) & 1) {
-                        const vec alo = *reinterpret_cast<const vec*>(ap_lo + (q * 64 + lane) * 8);
-                        dh = T::mfma(alo, bh[kb], dh);
-                    }
-                }
-                // D rows 16 mt + 4 g + r are this lane's x[mt / 2][4 (mt % 2) + r]
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    acc += (double)x[mt / 2][4 * (mt % 2) + r] * ((double)dh[r] + (double)dl[r] * (1.0 / T::LO));
-            }
-            part_h += acc / ((double)s * (double)s);
-        }
-        part_h = sum_lane_groups(part_h);
+        const auto load = [&](int c, int ri) { return Jh[(int64_t)(2 * c + ri) * ld + ec]; };
+        double part_h = sum_lane_groups(cs16_column<NC, T, AREG>(load, A, aop, aop_lo, lo_mask, lane));
         if (out_hel && g == 0 && valid) out_hel[e * n_good + h] = part_h * scale_hel;
         me += part_h;
     }
     if (g == 0 && valid) cs_store(me, e, n_evt, scale_avg, out, part);
+}
+
+// The same contractions inside an amplitude kernel whose wave (64 events of one helicity) holds
+// its jamps in LDS, Jl[(2c + re/im) * 64 + event]: for each of the four 16-event tiles the lanes
+// load the B operands from the other lanes' slots and run the same column body as the separate
+// kernels (so each |M_h|^2 is bitwise the same).  Returns this lane's event's D * |M_h|^2.  The
+// caller must have completed all jamp updates of the wave (a barrier) before the call.
+template <int NC, class JT>
+__device__ __forceinline__ double colour_sum_lds(const JT* Jl, const double* __restrict__ aop, int lane)
+{
+    constexpr int NT = cs64_tiles(NC);
+    static_assert(NT <= 24, "operands held in registers");
+    const int i = lane & 15, g = lane >> 4;
+    double A[NT];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) A[q] = aop[q * 64 + lane];
+    double mine = 0.0;
+#pragma unroll 1
+    for (int j = 0; j < 4; ++j) {  // events 16 j .. 16 j + 15
+        const auto load = [&](int c, int ri) { return Jl[(2 * c + ri) * 64 + 16 * j + i]; };
+        const double part_h = sum_lane_groups(cs64_column<NC, true>(load, A, aop, lane));
+        if (g == j) mine = part_h;  // lane 16 g + i is event 16 g + i
+    }
+    return mine;
+}
+template <int NC, class T>
+__device__ __forceinline__ double colour_sum_lds_h16(const float* Jl, const typename T::elem* __restrict__ aop,
+                                                     const typename T::elem* __restrict__ aop_lo, uint64_t lo_mask,
+                                                     int lane)
+{
+    typedef typename T::vec vec;
+    constexpr int NT = cs16_tiles(NC);
+    static_assert(NT <= 8, "operands held in registers");
+    const int i = lane & 15, g = lane >> 4;
+    vec A[NT];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) A[q] = *reinterpret_cast<const vec*>(aop + (q * 64 + lane) * 8);
+    double mine = 0.0;
+#pragma unroll 1
+    for (int j = 0; j < 4; ++j) {
+        const auto load = [&](int c, int ri) { return Jl[(2 * c + ri) * 64 + 16 * j + i]; };
+        const double part_h = sum_lane_groups(cs16_column<NC, T, true>(load, A, aop, aop_lo, lo_mask, lane));
+        if (g == j) mine = part_h;
+    }
+    return mine;
+}
+
+// The helicity sum after the fused colour sum, in the order of the separate colour-sum kernel
+// with the same helicity groups: within each group of hel_per_group consecutive helicities from
+// zero, then the groups in order (so the result is bitwise that of the separate kernels).
+// part_h[h][e] = D |M_h|^2.
+static __global__ __launch_bounds__(256) void hel_reduce_grouped(const double* __restrict__ part_h, int n_good,
+                                                                 int hel_per_group, int64_t n_evt, double scale,
+                                                                 double* __restrict__ out)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n_evt) return;
+    double s = 0.0;
+    for (int h0 = 0; h0 < n_good; h0 += hel_per_group) {
+        const int h1 = min(n_good, h0 + hel_per_group);
+        double m = 0.0;
+        for (int h = h0; h < h1; ++h) m += part_h[(int64_t)h * n_evt + e];
+        s += m;
+    }
+    out[e] = s * scale;
 }
 
 // out[e] = scale * sum over helicity groups of part[group][e], groups in order

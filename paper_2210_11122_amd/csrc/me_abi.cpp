@@ -287,9 +287,15 @@ int run_chunks(me_handle* h, int precision, const signed char* hel, int n_good, 
 {
     const me::ProcessDesc* P = h->P;
     const bool fp64 = precision == ME_FP64;
-    // the colour sum inside the amplitude kernel: plain FP64 |M|^2 only (the selection, the
+    // the colour sum inside the amplitude kernel: plain |M|^2 only (the selection, the
     // per-helicity output and the channel weights read the jamps)
-    const bool fused = fp64 && P->fused_colour && h->fuse_colour && !sel && !out_hel && !chan;
+    const bool fused = P->fused_colour && h->fuse_colour && !sel && !out_hel && !chan;
+    // the operand tables of the separate colour sum of this precision (small colour matrices:
+    // FP64 tiles in every precision)
+    me::FusedColour fcol{nullptr, nullptr, 0, precision};
+    if (precision == ME_FP64 || P->nc <= 6) fcol = {h->d_aop64, nullptr, 0, ME_FP64};
+    else if (precision == ME_MIXED_FP16) fcol.aop = h->d_aop16;
+    else fcol = {h->d_aopb, h->d_aopb_lo, h->lo_mask_b16, precision};
     void* jamp = scratch;
     double* part = reinterpret_cast<double*>(static_cast<char*>(scratch) + (size_t)chunk * jamp_bytes_per_event);
     for (int64_t c0 = 0; c0 < n; c0 += chunk) {
@@ -301,14 +307,16 @@ int run_chunks(me_handle* h, int precision, const signed char* hel, int n_good, 
         hipError_t e;
         if (fused) {
             // the amplitude kernel ends with the colour sum: D |M_h|^2 per (helicity, event) in the
-            // jamp scratch, then the helicity sum in a fixed order
-            e = P->launch_f64(m, nc, ld, hel, n_good, h->mt, h->g, static_cast<double*>(jamp), nullptr, nullptr,
-                              h->d_aop64, st);
+            // jamp scratch, then the helicity sum in the separate kernels' order (same groups)
+            e = fp64 ? P->launch_f64(m, nc, ld, hel, n_good, h->mt, h->g, static_cast<double*>(jamp), nullptr,
+                                     nullptr, &fcol, st)
+                     : P->launch_f32(m, nc, ld, hel, n_good, h->mt, h->g, static_cast<float*>(jamp), nullptr,
+                                     nullptr, &fcol, st);
             ta.done();
             if (e != hipSuccess) return fail(ME_EHIP, std::string("amplitude kernel: ") + hipGetErrorString(e));
             TimedLaunch tc(h, st, 1, timed);
-            hipLaunchKernelGGL(me::hel_reduce, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st,
-                               static_cast<const double*>(jamp), n_good, nc,
+            hipLaunchKernelGGL(me::hel_reduce_grouped, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st,
+                               static_cast<const double*>(jamp), n_good, hel_per_group, nc,
                                1.0 / ((double)P->colour_den * P->avg), out + c0);
             e = hipGetLastError();
             tc.done();
@@ -559,13 +567,6 @@ me_handle* me_create(const char* process, const double* masses, int n_masses, co
     h->chunk = std::max<int64_t>(64, chunk);
     // the helicity split is fixed per handle, so an event's result does not depend on the batch
     helicity_groups(P, h->n_good, h->chunk, &h->groups, &h->hel_per_group);
-    if (precision == ME_FP64 && P->fused_colour) {
-        // one helicity per group: the separate colour sum then adds the same per-helicity values
-        // in the same order as the fused kernel's helicity sum, so every FP64 path (and either
-        // setting of ME_OPT_FUSED_COLOUR) gives bitwise the same |M|^2
-        h->hel_per_group = 1;
-        h->groups = h->n_good;
-    }
     h->bytes_per_event = h->jamp_bytes_per_event + (h->groups > 1 ? h->groups * sizeof(double) : 0);
     return h;
 }
@@ -604,7 +605,7 @@ int me_info(const me_handle* h, me_info_t* out)
     out->n_order = P->n_order;
     out->helicity_groups = h->groups;
     out->lines_per_diagram = P->lines_per_diagram;
-    out->fused_colour = (h->precision == ME_FP64 && P->fused_colour && h->fuse_colour) ? 1 : 0;
+    out->fused_colour = (P->fused_colour && h->fuse_colour) ? 1 : 0;
     return ME_OK;
 }
 

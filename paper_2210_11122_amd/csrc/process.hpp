@@ -7,14 +7,23 @@ namespace me {
 
 // chan == nullptr: plain kernels; otherwise chan[n_evt] channel ids and sde[n_good][2][ld] the
 // per-lane single-diagram sums (channel, all)
-// aop (FP64 only, processes with fused_colour): the colour-matrix operands of colour_sum_f64;
-// when given, the kernel writes D |M_h|^2 to jamp[h * n_evt + event] instead of the jamps
+// The colour sum inside the amplitude kernel (processes with fused_colour): the operand tables
+// of the separate colour-sum kernel of the same form.  With a FusedColour the kernel writes
+// D |M_h|^2 as doubles to ((double*)jamp)[h * n_evt + event] instead of the jamps.
+struct FusedColour {
+    const void* aop;     // FP64 tiles (FP64 kernel) or FP16 / BF16 hi tiles (FP32 kernel)
+    const void* aop_lo;  // BF16 lo tiles (BF16 form)
+    uint64_t lo_mask;    // tiles with a non-zero lo part (BF16 form)
+    int form;            // ME_FP64, ME_MIXED_FP16 or ME_MIXED_BF16 (me.h)
+};
+
+// fc: null, or the fused colour sum (then chan must be null)
 typedef hipError_t (*amp_launch_f64)(const double* mom, int64_t n_evt, int64_t ld, const signed char* hel,
                                      int n_good, double mt, double g, double* jamp, const int* chan, double* sde,
-                                     const double* aop, hipStream_t st);
+                                     const FusedColour* fc, hipStream_t st);
 typedef hipError_t (*amp_launch_f32)(const double* mom, int64_t n_evt, int64_t ld, const signed char* hel,
                                      int n_good, double mt, double g, float* jamp, const int* chan, double* sde,
-                                     const double* aop, hipStream_t st);  // aop: must be null
+                                     const FusedColour* fc, hipStream_t st);
 
 struct ProcessDesc {
     const char* name;
@@ -37,7 +46,7 @@ struct ProcessDesc {
     const int* diagram_lines;  // n_diagrams x lines_per_diagram internal-line masks (0-padded)
     int lines_per_diagram;
     int sde_supported;         // single-diagram channel weights available
-    int fused_colour;          // the FP64 amplitude kernel can do the colour sum itself (aop)
+    int fused_colour;          // the amplitude kernels can do the colour sum themselves (FusedColour)
     amp_launch_f64 launch_f64;
     amp_launch_f32 launch_f32;
 };

@@ -440,13 +440,15 @@ class Process:
             L.append(f"// {len(kernels)} segment kernels, {self.segments[1]}-slot LDS jamp window, "
                      f"{self.nslot} partial jamp slots; executed flops per lane {self.flops_exec} "
                      f"(algorithmic {fl}).")
-        # the FP64 kernel can finish with the colour sum when its jamps are in LDS and complete
-        fused = bool(jamps_in_lds) and not self.segments and self.kind != "ee"
+        # a kernel that ends with all jamps of its lane (no window, no partial slots) can finish
+        # with the colour sum itself
+        fused = not self.segments
         self.fused_colour = fused
         L.append('#include "../helas.hpp"')
         L.append('#include "../process.hpp"')
         if fused:
             L.append('#include "../colorsum.hpp"')
+            L.append('#include "me.h"')
         L.append("namespace me {")
         L.append(f"namespace proc_{nm} {{")
         L.append(f"constexpr int NPAR = {self.npar};")
@@ -497,13 +499,18 @@ class Process:
             L += self._reduce_text()
         L.append("template <class R>")
         L.append("static hipError_t launch(const double* mom, int64_t n_evt, int64_t ld, const signed char* hel, "
-                 "int n_good, double mt, double gs, R* jamp, const int* chan, double* sde, const double* aop, "
+                 "int n_good, double mt, double gs, R* jamp, const int* chan, double* sde, const FusedColour* fc, "
                  "hipStream_t st)")
         L.append("{")
         if not fused:
-            L.append("    if (aop) return hipErrorInvalidValue;  // no fused colour sum for this process")
+            L.append("    if (fc) return hipErrorInvalidValue;  // no fused colour sum for this process")
         else:
-            L.append("    if (aop && (sizeof(R) != 8 || chan)) return hipErrorInvalidValue;")
+            if nc > 6:
+                L.append("    if (fc && (chan || !fc->aop || (sizeof(R) == 8) != (fc->form == ME_FP64))) "
+                         "return hipErrorInvalidValue;")
+            else:
+                L.append("    if (fc && (chan || !fc->aop || fc->form != ME_FP64)) return hipErrorInvalidValue;")
+            L.append("    const FusedColour none{nullptr, nullptr, 0, 0};")
         L.append("    int64_t blocks = ((n_evt + 63) / 64) * n_good;")
         L.append("    if (blocks == 0) return hipSuccess;")
         for kname, _, _, _ in kernels:
@@ -517,11 +524,11 @@ class Process:
                 L.append("    }")
             else:
                 L.append("    if (chan)")
-                tail = ", nullptr" if fused else ""
+                tail = ", none" if fused else ""
                 L.append(f"        hipLaunchKernelGGL(({kname}<R, true>), dim3((unsigned)blocks), dim3(64), 0, st, mom, n_evt, "
                          f"ld, hel, n_good, mt, gs, jamp, chan, sde{tail});")
                 L.append("    else")
-                tail = ", aop" if fused else ""
+                tail = ", fc ? *fc : none" if fused else ""
                 L.append(f"        hipLaunchKernelGGL(({kname}<R, false>), dim3((unsigned)blocks), dim3(64), 0, st, mom, n_evt, "
                          f"ld, hel, n_good, mt, gs, jamp, nullptr, nullptr{tail});")
         if self.segments:
@@ -562,7 +569,7 @@ class Process:
         L.append(f"__global__ __launch_bounds__({bounds}) void {kname}(const double* __restrict__ mom, int64_t n_evt, "
                  "int64_t ld, const signed char* __restrict__ hel, int n_good, double mt, double gs, "
                  "R* __restrict__ jamp, const int* __restrict__ chan, double* __restrict__ sde"
-                 + (", const double* __restrict__ aop)" if fused else ")"))
+                 + (", FusedColour fc)" if fused else ")"))
         L.append("{")
         L.append("    __shared__ double lds[4 * NPAR * 64];")
         L.append("    const int lane = threadIdx.x;")
@@ -635,13 +642,33 @@ class Process:
         L.append("    }")
         if mode == "jamps":
             if fused:
-                L.append("    if constexpr (sizeof(R) == 8) {")
-                L.append("        if (aop) {  // colour sum here: D |M_h|^2 of this lane's event, to jamp[h][event]")
-                L.append("            __syncthreads();  // every jamp update of the wave has completed")
-                L.append("            const double me_h = colour_sum_lds<NC>(Jl, aop, lane);")
-                L.append("            if (e < n_evt) jamp[(int64_t)h * n_evt + e] = me_h;")
-                L.append("            return;")
-                L.append("        }")
+                L.append("    if (fc.aop) {  // colour sum here: D |M_h|^2 of this lane's event, to [h][event]")
+                if jamps_in_lds:
+                    src = "Jl"
+                    L.append("        __syncthreads();  // every jamp update of the wave has completed")
+                else:
+                    # register jamps go to the momentum area of LDS, which is no longer read
+                    src = "Js"
+                    L.append("        __syncthreads();")
+                    L.append("        R* Js = reinterpret_cast<R*>(lds);")
+                    L.append("#pragma unroll")
+                    L.append("        for (int s = 0; s < 2 * NC; ++s) Js[s * 64 + lane] = Jr[s];")
+                    L.append("        __syncthreads();")
+                L.append("        double me_h;")
+                if self.nc > 6:
+                    L.append("        if constexpr (sizeof(R) == 8)")
+                    L.append(f"            me_h = colour_sum_lds<NC>({src}, static_cast<const double*>(fc.aop), lane);")
+                    L.append("        else if (fc.form == ME_MIXED_BF16)")
+                    L.append(f"            me_h = colour_sum_lds_h16<NC, Bf16Terms>({src}, static_cast<const __bf16*>(fc.aop), "
+                             "static_cast<const __bf16*>(fc.aop_lo), fc.lo_mask, lane);")
+                    L.append("        else")
+                    L.append(f"            me_h = colour_sum_lds_h16<NC, Fp16Terms>({src}, static_cast<const _Float16*>(fc.aop), "
+                             "static_cast<const _Float16*>(fc.aop), 0, lane);")
+                else:
+                    # small colour matrices: FP64 tiles in every precision, as in the separate kernel
+                    L.append(f"        me_h = colour_sum_lds<NC>({src}, static_cast<const double*>(fc.aop), lane);")
+                L.append("        if (e < n_evt) reinterpret_cast<double*>(jamp)[(int64_t)h * n_evt + e] = me_h;")
+                L.append("        return;")
                 L.append("    }")
             # all reads first (one wait), then the stores
             L.append("    R jo[2 * NC];")

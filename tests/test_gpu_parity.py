@@ -151,17 +151,18 @@ def test_result_independent_of_batch(name, precision):
     assert np.array_equal(full[:37], head) and np.array_equal(full[n - 101:], tail)
 
 
-def test_fused_colour_sum_equals_separate_kernel():
-    """gg_ttgg FP64: the colour sum inside the amplitude kernel (the default) and the separate
-    colour-sum kernel give bitwise the same |M|^2 (same per-helicity products, helicities added
-    one by one in the same order), over two launches with a ragged tail"""
-    import ctypes
+@pytest.mark.parametrize("name,precision", [("gg_ttgg", "fp64"), ("gg_ttgg", "mixed_fp16"), ("gg_ttgg", "mixed_bf16"),
+                                            ("gg_ttg", "fp64"), ("gg_ttg", "mixed_fp16"), ("gg_tt", "fp64"),
+                                            ("ee_mumu", "fp64"), ("ee_mumu_z", "mixed_bf16"), ("gg_gg", "fp64")])
+def test_fused_colour_sum_equals_separate_kernel(name, precision):
+    """the colour sum inside the amplitude kernel (the default) and the separate colour-sum
+    kernel give bitwise the same |M|^2 (same per-helicity tiles and operand splits, helicities
+    added in the same groups and order); gg_ttgg over two launches, all with a ragged tail"""
     from paper_2210_11122_amd import binding
-    name = "gg_ttgg"
-    proc = make_process(name)
-    assert proc.info["fused_colour"] == 1 and proc.info["helicity_groups"] == proc.info["n_good_hel"]
-    n = proc.info["chunk_events"] + 777
-    print(f"case fused colour sum {name} n={n}", flush=True)
+    proc = make_process(name, precision)
+    assert proc.info["fused_colour"] == 1
+    n = proc.info["chunk_events"] + 777 if name == "gg_ttgg" else 20011
+    print(f"case fused colour sum {name} {precision} n={n}", flush=True)
     x = proc.rambo(5, W.sqrt_s(name), n)
     fused = proc.sigma(x).cpu().numpy()
     proc.set_fused_colour(False)
@@ -240,5 +241,5 @@ def test_info_counts():
                              ("gg_ttgg", 123, 24, 64), ("gg_ttggg", 1240, 120, 128)]:
         i = make_process(name).info
         assert (i["n_diagrams"], i["n_colors"], i["n_hel"]) == (nd, nc, nh)
-        assert i["fused_colour"] == (1 if name == "gg_ttgg" else 0)
-    assert make_process("gg_ttgg", "mixed_fp16").info["fused_colour"] == 0
+        assert i["fused_colour"] == (0 if name == "gg_ttggg" else 1)
+    assert make_process("gg_ttggg", "mixed_fp16").info["fused_colour"] == 0

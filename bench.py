@@ -275,6 +275,8 @@ def main():
                                     "p99": float(np.quantile(rel, 0.99)), "p999": float(np.quantile(rel, 0.999))},
                 "latency_ms": {"p50": quantile(latm, 0.5), "p99": quantile(latm, 0.99)},
                 "amplitude_kernel_tflops": ach_m, "amplitude_kernel_frac_fp32_peak": ach_m / FP32_VALU_PEAK_TFLOPS,
+                "colour_sum_in_amplitude_kernel": bool(pm.info["fused_colour"]),
+                # with the colour sum in the amplitude kernel: the helicity-sum kernel's time
                 "colour_sum_ms_per_step": ms_cs_m / args.steps,
             }
             log(f"{prec}: {msm:.3f} ms/step, {mesm:.4g} MEs/s, rel err max {rel.max():.2e} "

@@ -102,10 +102,11 @@ template <int NC, bool AREG, class Load>
 __device__ __forceinline__ double cs64_column(const Load& load, const double* A, const double* aop, int lane)
 {
     constexpr int MT = (NC + 15) / 16, KT = (NC + 3) / 4;
+    // the real/imaginary loop stays rolled for the large matrices (register pressure)
+    constexpr int RI_UNROLL = NC > 24 ? 1 : 2;
     const int g = lane >> 4;
     double part_h = 0.0;
-    // the real/imaginary loop stays rolled for the large matrices (register pressure)
-#pragma unroll (NC > 24 ? 1 : 2)
+#pragma unroll RI_UNROLL
     for (int ri = 0; ri < 2; ++ri) {
         // this lane's B elements: colours c = 4 kt + g, which are also its D rows
         double b[KT];

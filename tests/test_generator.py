@@ -188,6 +188,59 @@ def test_window_program_reproduces_direct_accumulation():
     assert np.allclose(red, direct, atol=1e-12 * np.abs(direct).max())
 
 
+def test_emitted_window_kernels_and_reduction_accumulate_every_jamp():
+    """interpret the emitted gg_ttggg segment kernels macro by macro, in program order (LDS
+    window slots: JADD, JTAKE, JLAST; registers; partial slots in HBM: JPUT), then the emitted
+    reduction tables (slot_offset, slot_list); with random amplitudes the reduced jamps must
+    equal direct accumulation, every partial slot written exactly once"""
+    import re
+    P = emit.Process("gg_ttggg")
+    src = P.source()
+    perm_index = {tuple(p): i for i, p in enumerate(P.perms)}
+    jsets = [set(perm_index[q] for q in P.jcoef[i]) for i in range(len(P.diagrams))]
+    n_seg, window, beta = P.segments
+    segs = D.segment_plan(P.plan, jsets, n_seg, beta, window)
+    rng = np.random.default_rng(1)
+    amp = rng.normal(size=len(P.diagrams)) + 1j * rng.normal(size=len(P.diagrams))
+    direct = np.zeros(P.nc, complex)
+    for di in range(len(P.diagrams)):
+        for q, c in P.jcoef[di].items():
+            direct[perm_index[q]] += complex(c.re, c.im) * amp[di]
+    partial = np.full(P.nslot, np.nan + 1j * np.nan)
+    written = np.zeros(P.nslot, int)
+    jadd = re.compile(r"JADD\((\d+), ([01]), ([^;]*)\);")
+    macro = re.compile(r"(JTAKE|JLAST|JPUT)\((\d+), (\d+)\);")
+    for k, order in enumerate(segs):
+        text = P.extra_files[f"proc_gg_ttggg_amp_seg{k}.hip"]
+        body = text[text.index("#define SDEACC"):text.index("if constexpr (SDE) {\n        if (e < n_evt)")]
+        win = np.zeros(window, complex)
+        fr = {}
+        it = iter(order)
+        a = None
+        for line in body.splitlines()[1:]:
+            if re.match(r"\s*a = amp", line):
+                a = amp[next(it)[0]]
+                continue
+            for s_, ri, v in jadd.findall(line):
+                val = eval(v.replace("(R)", "").replace("a.r", "ar").replace("a.i", "ai"), {"ar": a.real, "ai": a.imag})
+                win[int(s_)] += val if ri == "0" else 1j * val
+            for m, x, y in macro.findall(line):
+                x, y = int(x), int(y)
+                if m == "JTAKE":
+                    fr[y], win[x] = win[x], 0
+                elif m == "JLAST":
+                    fr[y] = win[x]
+                else:
+                    partial[x] = fr.pop(y)
+                    written[x] += 1
+        assert next(it, None) is None and not fr
+    assert np.all(written == 1)
+    offs = [int(v) for v in re.search(r"slot_offset\[NC \+ 1\] = \{([^}]*)\}", src).group(1).split(",")]
+    lst = [int(v) for v in re.search(r"slot_list\[NSLOT\] = \{([^}]*)\}", src).group(1).split(",")]
+    red = np.array([sum(partial[lst[i]] for i in range(offs[c], offs[c + 1])) for c in range(P.nc)])
+    assert np.allclose(red, direct, rtol=0, atol=1e-12 * np.abs(direct).max())
+
+
 @pytest.mark.parametrize("name", ["gg_tt", "gg_ttg", "gg_ttgg"])
 def test_single_diagram_data_matches_oracle(name):
     """per Feynman diagram (matched by internal lines) the generator's colour weights

@@ -427,17 +427,19 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t w, int64_t n)
 // Stage the momenta of events [e0, e0+64) (layout [event][particle][4], double) through
 // LDS with coalesced 16-byte loads, into component pairs lds2[2 i + (E, px) | (py, pz)][lane]
 // (16 bytes per lane, so a lane reads a four-momentum with two conflict-free 16-byte LDS
-// loads); lanes past n_evt read zeros.
-template <int NPAR>
+// loads); lanes past n_evt read zeros.  WG waves of a workgroup (tid = threadIdx.x) share the
+// work and the staged block.
+template <int NPAR, int WG = 1>
 __device__ __forceinline__ void stage_momenta(const double* __restrict__ mom, int64_t n_evt, int64_t e0,
-                                              double* lds, int lane)
+                                              double* lds, int tid)
 {
     constexpr int NCOMP = 4 * NPAR;
+    static_assert((NCOMP / 2) % WG == 0, "whole loads per thread");
     const double2* src = reinterpret_cast<const double2*>(mom + e0 * NCOMP);
     const int64_t n_here = (n_evt - e0) < 64 ? (n_evt - e0) : 64;
 #pragma unroll
-    for (int k = 0; k < NCOMP / 2; ++k) {
-        int f = lane + 64 * k;        // double2 index within the block
+    for (int k = 0; k < NCOMP / 2 / WG; ++k) {
+        int f = tid + 64 * WG * k;    // double2 index within the block
         int ev = (2 * f) / NCOMP;     // event within the block
         int c = (2 * f) % NCOMP;      // first component
         double2 v = {0.0, 0.0};

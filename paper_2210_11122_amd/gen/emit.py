@@ -37,6 +37,9 @@ PIN_MOMENTA = True
 # name -> minimum waves per SIMD asked of the compiler for the (FP64, FP32) amplitude kernels
 # (the second __launch_bounds__ argument: it caps the registers per lane at 512 / waves)
 MIN_WAVES = {"gg_ttgg": (1, 2), "gg_ttggg": (1, 2)}
+# name -> waves per workgroup (FP64, FP32 kernels): consecutive helicities of one 64-event block
+# that share the staged momenta (less LDS per wave where LDS, not registers, limits the waves)
+WAVES_PER_GROUP = {"gg_ttgg": (1, 2), "gg_ttggg": (1, 2)}
 ALL_PROCESSES = ["ee_mumu", "gg_tt", "gg_ttg", "gg_ttgg", "gg_ttggg", "gg_gg", "ee_mumu_z"]
 # electroweak constants of ee -> mumu with Z exchange: M_Z, Gamma_Z, M_W [GeV]
 EW_MZ, EW_WZ, EW_MW = 91.188, 2.441404, 80.419
@@ -464,16 +467,17 @@ class Process:
                      f"constexpr int NPAR = {self.npar};", f"constexpr int NC = {nc};",
                      f"constexpr int NSLOT = {self.nslot};"]
                 F += self._kernel_text(kname, body, nwin, mode, jamps_in_lds, jamp_mode, first=(kname == "amp_seg0"))
-                for R, tag in (("double", "f64"), ("float", "f32")):
+                g64, g32 = WAVES_PER_GROUP.get(self.name, (1, 1))
+                for R, tag, wg in (("double", "f64", g64), ("float", "f32", g32)):
                     F.append(f"hipError_t {kname}_launch_{tag}(const double* mom, int64_t n_evt, int64_t ld, "
                              f"const signed char* hel, int n_good, double mt, double gs, {R}* jamp, const int* chan, "
                              "double* sde, hipStream_t st, int64_t blocks)")
                     F.append("{")
                     F.append("    if (chan)")
-                    F.append(f"        hipLaunchKernelGGL(({kname}<{R}, true>), dim3((unsigned)blocks), dim3(64), 0, st, mom, "
+                    F.append(f"        hipLaunchKernelGGL(({kname}<{R}, true>), dim3((unsigned)blocks), dim3({64 * wg}), 0, st, mom, "
                              "n_evt, ld, hel, n_good, mt, gs, jamp, chan, sde);")
                     F.append("    else")
-                    F.append(f"        hipLaunchKernelGGL(({kname}<{R}, false>), dim3((unsigned)blocks), dim3(64), 0, st, mom, "
+                    F.append(f"        hipLaunchKernelGGL(({kname}<{R}, false>), dim3((unsigned)blocks), dim3({64 * wg}), 0, st, mom, "
                              "n_evt, ld, hel, n_good, mt, gs, jamp, nullptr, nullptr);")
                     F.append("    return hipGetLastError();")
                     F.append("}")
@@ -511,7 +515,9 @@ class Process:
             else:
                 L.append("    if (fc && (chan || !fc->aop || fc->form != ME_FP64)) return hipErrorInvalidValue;")
             L.append("    const FusedColour none{nullptr, nullptr, 0, 0};")
-        L.append("    int64_t blocks = ((n_evt + 63) / 64) * n_good;")
+        g64, g32 = WAVES_PER_GROUP.get(self.name, (1, 1))
+        L.append(f"    constexpr int WG = sizeof(R) == 8 ? {g64} : {g32};  // waves (helicities) per workgroup")
+        L.append("    int64_t blocks = ((n_evt + 63) / 64) * ((n_good + WG - 1) / WG);")
         L.append("    if (blocks == 0) return hipSuccess;")
         for kname, _, _, _ in kernels:
             if self.segments:
@@ -525,11 +531,11 @@ class Process:
             else:
                 L.append("    if (chan)")
                 tail = ", none" if fused else ""
-                L.append(f"        hipLaunchKernelGGL(({kname}<R, true>), dim3((unsigned)blocks), dim3(64), 0, st, mom, n_evt, "
+                L.append(f"        hipLaunchKernelGGL(({kname}<R, true>), dim3((unsigned)blocks), dim3(64 * WG), 0, st, mom, n_evt, "
                          f"ld, hel, n_good, mt, gs, jamp, chan, sde{tail});")
                 L.append("    else")
                 tail = ", fc ? *fc : none" if fused else ""
-                L.append(f"        hipLaunchKernelGGL(({kname}<R, false>), dim3((unsigned)blocks), dim3(64), 0, st, mom, n_evt, "
+                L.append(f"        hipLaunchKernelGGL(({kname}<R, false>), dim3((unsigned)blocks), dim3(64 * WG), 0, st, mom, n_evt, "
                          f"ld, hel, n_good, mt, gs, jamp, nullptr, nullptr{tail});")
         if self.segments:
             L.append("    hipLaunchKernelGGL(reduce_kernel<R>, dim3((unsigned)((n_evt + 255) / 256), (unsigned)n_good), "
@@ -565,19 +571,28 @@ class Process:
         L = []
         L.append("template <class R, bool SDE>")
         w64, w32 = MIN_WAVES.get(self.name, (1, 1))
-        bounds = "64" if (w64, w32) == (1, 1) else f"64, (sizeof(R) == 8 ? {w64} : {w32})"
+        g64, g32 = WAVES_PER_GROUP.get(self.name, (1, 1))
+        if (g64, g32) != (1, 1) and not (jamps_in_lds or mode == "slots"):
+            # register jamps are staged in the (shared) momentum area for the colour sum
+            raise ValueError("several waves per workgroup need per-wave LDS jamps")
+        threads = "64" if (g64, g32) == (1, 1) else f"64 * (sizeof(R) == 8 ? {g64} : {g32})"
+        bounds = threads if (w64, w32) == (1, 1) else f"{threads}, (sizeof(R) == 8 ? {w64} : {w32})"
         L.append(f"__global__ __launch_bounds__({bounds}) void {kname}(const double* __restrict__ mom, int64_t n_evt, "
                  "int64_t ld, const signed char* __restrict__ hel, int n_good, double mt, double gs, "
                  "R* __restrict__ jamp, const int* __restrict__ chan, double* __restrict__ sde"
                  + (", FusedColour fc)" if fused else ")"))
         L.append("{")
+        L.append(f"    constexpr int WG = sizeof(R) == 8 ? {g64} : {g32};  // waves per workgroup")
         L.append("    __shared__ double lds[4 * NPAR * 64];")
-        L.append("    const int lane = threadIdx.x;")
+        L.append("    const int lane = threadIdx.x & 63;")
         L.append("    const int64_t w = xcd_remap(blockIdx.x, gridDim.x);")
-        L.append("    const int64_t e0 = (w / n_good) * 64;")
-        L.append("    const int h = (int)(w % n_good);")
+        L.append("    const int hpb = (n_good + WG - 1) / WG;  // workgroups per event block")
+        L.append("    const int64_t e0 = (w / hpb) * 64;")
+        L.append("    const int hr = (int)(w % hpb) * WG + (int)(threadIdx.x >> 6);")
+        L.append("    const bool live = hr < n_good;  // a spare wave of the last group repeats a helicity, writes nothing")
+        L.append("    const int h = live ? hr : n_good - 1;")
         L.append("    const int64_t e = e0 + lane;  // < ld: ld is a multiple of 64 covering the grid")
-        L.append("    stage_momenta<NPAR>(mom, n_evt, e0, lds, lane);")
+        L.append("    stage_momenta<NPAR, WG>(mom, n_evt, e0, lds, threadIdx.x);")
         L.append("#define PM(i) lds_p4(lds, i, lane)")
         L.append("    int lam[NPAR];")
         L.append("#pragma unroll")
@@ -586,7 +601,8 @@ class Process:
         if jamps_in_lds or mode == "slots":
             acc = "double" if jamp_mode == "atomic64" else "R"
             L.append(f"    // jamps accumulate in LDS, one private slot per lane ({jamp_mode})")
-            L.append(f"    __shared__ {acc} Jl[2 * NW * 64];")
+            L.append(f"    __shared__ {acc} Jl_wg[WG * 2 * NW * 64];")
+            L.append(f"    {acc}* const Jl = Jl_wg + (threadIdx.x >> 6) * (2 * NW * 64);")
             L.append("#pragma unroll")
             if jamp_mode == "auto":
                 L.append("    for (int s = 0; s < 2 * NW; ++s) jamp_zero<R>(&Jl[s * 64 + lane]);")
@@ -619,8 +635,8 @@ class Process:
             # to its partial slot later, once the read has long completed
             L.append("#define JTAKE(s, k) const R fr##k = JGET(s, 0), fi##k = JGET(s, 1); JZERO(s, 0); JZERO(s, 1)")
             L.append("#define JLAST(s, k) const R fr##k = JGET(s, 0), fi##k = JGET(s, 1)")
-            L.append("#define JPUT(p, k) do { po[(int64_t)(2 * (p)) * ld] = fr##k; "
-                     "po[(int64_t)(2 * (p) + 1) * ld] = fi##k; } while (0)")
+            L.append("#define JPUT(p, k) do { if (live) { po[(int64_t)(2 * (p)) * ld] = fr##k; "
+                     "po[(int64_t)(2 * (p) + 1) * ld] = fi##k; } } while (0)")
         L.append("    cx<R> a;")
         L.append("    int ch = -1;")
         L.append("    double sde_ch = 0.0, sde_all = 0.0;")
@@ -630,7 +646,7 @@ class Process:
                  "sde_all += w_; sde_ch += ((d) == ch) ? w_ : 0.0; } } while (0)")
         L.extend(body)
         L.append("    if constexpr (SDE) {")
-        L.append("        if (e < n_evt) {")
+        L.append("        if (live && e < n_evt) {")
         L.append("            double* so = sde + (int64_t)h * 2 * ld + e;")
         if first:
             L.append("            so[0] = sde_ch;")
@@ -667,7 +683,7 @@ class Process:
                 else:
                     # small colour matrices: FP64 tiles in every precision, as in the separate kernel
                     L.append(f"        me_h = colour_sum_lds<NC>({src}, static_cast<const double*>(fc.aop), lane);")
-                L.append("        if (e < n_evt) reinterpret_cast<double*>(jamp)[(int64_t)h * n_evt + e] = me_h;")
+                L.append("        if (live && e < n_evt) reinterpret_cast<double*>(jamp)[(int64_t)h * n_evt + e] = me_h;")
                 L.append("        return;")
                 L.append("    }")
             # all reads first (one wait), then the stores
@@ -677,7 +693,7 @@ class Process:
             L.append("        jo[2 * s] = JGET(s, 0);")
             L.append("        jo[2 * s + 1] = JGET(s, 1);")
             L.append("    }")
-            L.append("    if (e < n_evt) {")
+            L.append("    if (live && e < n_evt) {")
             L.append("        R* o = jamp + (int64_t)h * (2 * NC) * ld + e;")
             L.append("#pragma unroll")
             L.append("        for (int s = 0; s < 2 * NC; ++s) o[s * ld] = jo[s];")

@@ -212,7 +212,7 @@ def test_emitted_window_kernels_and_reduction_accumulate_every_jamp():
     macro = re.compile(r"(JTAKE|JLAST|JPUT)\((\d+), (\d+)\);")
     for k, order in enumerate(segs):
         text = P.extra_files[f"proc_gg_ttggg_amp_seg{k}.hip"]
-        body = text[text.index("#define SDEACC"):text.index("if constexpr (SDE) {\n        if (e < n_evt)")]
+        body = text[text.index("#define SDEACC"):text.index("\n    if constexpr (SDE) {\n")]
         win = np.zeros(window, complex)
         fr = {}
         it = iter(order)

@@ -434,14 +434,15 @@ __device__ __forceinline__ void stage_momenta(const double* __restrict__ mom, in
                                               double* lds, int tid)
 {
     constexpr int NCOMP = 4 * NPAR;
-    static_assert((NCOMP / 2) % WG == 0, "whole loads per thread");
+    constexpr int NLOAD = 64 * NCOMP / 2;  // double2 elements of the block
     const double2* src = reinterpret_cast<const double2*>(mom + e0 * NCOMP);
     const int64_t n_here = (n_evt - e0) < 64 ? (n_evt - e0) : 64;
 #pragma unroll
-    for (int k = 0; k < NCOMP / 2 / WG; ++k) {
-        int f = tid + 64 * WG * k;    // double2 index within the block
-        int ev = (2 * f) / NCOMP;     // event within the block
-        int c = (2 * f) % NCOMP;      // first component
+    for (int k = 0; k < (NLOAD + 64 * WG - 1) / (64 * WG); ++k) {
+        const int f = tid + 64 * WG * k;  // double2 index within the block
+        if (NLOAD % (64 * WG) != 0 && f >= NLOAD) break;
+        const int ev = (2 * f) / NCOMP;   // event within the block
+        const int c = (2 * f) % NCOMP;    // first component
         double2 v = {0.0, 0.0};
         if (ev < n_here) v = src[f];
         reinterpret_cast<double2*>(lds)[(c / 2) * 64 + ev] = v;   // c is even: one component pair

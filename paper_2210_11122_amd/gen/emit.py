@@ -29,7 +29,7 @@ FLOPS = {
 
 QCD_PROCESSES = {"gg_tt": 2, "gg_ttg": 3, "gg_ttgg": 4, "gg_ttggg": 5}
 # name -> (segment kernels, LDS jamp-window slots, weight of window misses in the schedule)
-SEGMENTS = {"gg_ttggg": (14, 24, 1.0)}
+SEGMENTS = {"gg_ttggg": (14, 28, 1.0)}
 # read each amplitude step's momenta from LDS ahead of the previous step's jamp updates
 PREFETCH_MOMENTA = True
 # and keep the compiler from summing them before the step that uses them
@@ -39,7 +39,7 @@ PIN_MOMENTA = True
 MIN_WAVES = {"gg_ttgg": (1, 2), "gg_ttggg": (1, 2)}
 # name -> waves per workgroup (FP64, FP32 kernels): consecutive helicities of one 64-event block
 # that share the staged momenta (less LDS per wave where LDS, not registers, limits the waves)
-WAVES_PER_GROUP = {"gg_ttgg": (1, 2), "gg_ttggg": (1, 2)}
+WAVES_PER_GROUP = {"gg_ttgg": (1, 2), "gg_ttggg": (2, 4)}
 ALL_PROCESSES = ["ee_mumu", "gg_tt", "gg_ttg", "gg_ttgg", "gg_ttggg", "gg_gg", "ee_mumu_z"]
 # electroweak constants of ee -> mumu with Z exchange: M_Z, Gamma_Z, M_W [GeV]
 EW_MZ, EW_WZ, EW_MW = 91.188, 2.441404, 80.419

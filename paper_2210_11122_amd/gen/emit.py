@@ -36,7 +36,7 @@ PREFETCH_MOMENTA = True
 PIN_MOMENTA = True
 # name -> minimum waves per SIMD asked of the compiler for the (FP64, FP32) amplitude kernels
 # (the second __launch_bounds__ argument: it caps the registers per lane at 512 / waves)
-MIN_WAVES = {"gg_ttgg": (1, 2), "gg_ttggg": (1, 2)}
+MIN_WAVES = {"gg_tt": (4, 5), "gg_ttg": (2, 3), "gg_ttgg": (1, 2), "gg_ttggg": (1, 2)}
 # name -> waves per workgroup (FP64, FP32 kernels): consecutive helicities of one 64-event block
 # that share the staged momenta (less LDS per wave where LDS, not registers, limits the waves)
 WAVES_PER_GROUP = {"gg_ttgg": (1, 2), "gg_ttggg": (2, 4)}

@@ -258,3 +258,36 @@ def test_single_diagram_data_matches_oracle(name):
     assert set(g) == set(o) and len(g) == P.n_diagrams
     for key in g:
         assert sorted(g[key]) == sorted(o[key])
+
+
+@pytest.mark.parametrize("name", ["gg_ttgg", "gg_ttggg"])
+def test_spare_waves_write_nothing(name):
+    """with several waves (helicities) per workgroup, a spare wave of an odd last group repeats
+    a helicity; every global store of the emitted kernels must sit inside a `live` guard (the
+    good helicity counts of these processes are even, so the GPU tests never run a spare wave)"""
+    import re
+    assert emit.WAVES_PER_GROUP[name] != (1, 1)
+    P = emit.Process(name)
+    src = P.source()
+    store = re.compile(r"(\b(o|so|po)\s*\[[^]]*\]\s*\+?=[^=])|(reinterpret_cast<double\*>\(jamp\)\[[^]]*\]\s*=[^=])")
+    n_stores = 0
+    for text in [src] + list(getattr(P, "extra_files", {}).values()):
+        for m in re.finditer(r"__global__[^{]*void (amp_kernel|amp_seg\d+)\([^{]*\{\n", text):
+            body = text[m.end():text.index("\n}\n", m.end())]
+            guarded = []   # per open brace: does its block sit under a `live` test
+            for line in body.splitlines():
+                code = line.strip()
+                if code.startswith("#define"):
+                    if code.startswith("#define JPUT"):
+                        assert "if (live)" in code, code
+                    continue
+                if store.search(code):
+                    n_stores += 1
+                    assert "live" in code or any(guarded), code
+                for ch in code:
+                    if ch == "{":
+                        guarded.append("if (live" in code)
+                    elif ch == "}":
+                        guarded.pop()
+            assert not guarded
+    assert n_stores > 0

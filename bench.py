@@ -255,6 +255,12 @@ def main():
         }),
     }
 
+    if info["n_partial_slots"] > 0 and n_evt > info["chunk_events"] // 2:
+        # chunks alternate between two streams, so two amplitude launches share the GPU and each
+        # takes longer: the per-launch rate above is halved; the step-time rate is a lower bound
+        # on the throughput of the amplitude work (the step also holds the colour sum)
+        result["roofline"]["concurrent_streams"] = 2
+        result["roofline"]["achieved_per_step_time"] = flops_kernel_step / (ms64 / 1e3) / 1e12
     tr = measured_traffic(name)
     if tr is not None:
         result["roofline"]["traffic"] = tr["hbm_bytes_per_launch"]
@@ -279,6 +285,9 @@ def main():
                 # with the colour sum in the amplitude kernel: the helicity-sum kernel's time
                 "colour_sum_ms_per_step": ms_cs_m / args.steps,
             }
+            if pm.info["n_partial_slots"] > 0 and n_evt > pm.info["chunk_events"] // 2:
+                # two streams: per-launch times overlap (as for FP64 above)
+                result[prec]["amplitude_kernel_tflops_per_step_time"] = flops_amp_step / (msm / 1e3) / 1e12
             log(f"{prec}: {msm:.3f} ms/step, {mesm:.4g} MEs/s, rel err max {rel.max():.2e} "
                 f"median {np.median(rel):.2e}, colour sum {ms_cs_m / args.steps:.3f} ms/step")
             del pm

@@ -11,9 +11,11 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <unordered_map>
+#include <utility>
 #include <vector>
 
 #include "colorsum.hpp"
@@ -45,6 +47,39 @@ struct Scratch {
     void* ptr = nullptr;
     size_t bytes = 0;
 };
+
+// Two internal streams per (device, caller stream): the chunks of a process with segment
+// kernels alternate between them, so that the reduction of one chunk (bound by HBM) runs beside
+// the segment kernels of the next (bound by the VALU).  One pair serves every handle and lives
+// until the process ends: a pair per handle would crowd the device's few hardware queues, and
+// streams that share a queue run one after the other.
+struct Helpers {
+    std::mutex mu;   // one call's record/launch/wait sequence at a time
+    hipStream_t s[2] = {nullptr, nullptr};
+    hipEvent_t start = nullptr, done[2] = {nullptr, nullptr};
+};
+std::mutex g_helpers_mu;
+std::map<std::pair<int, hipStream_t>, Helpers> g_helpers;
+
+// the helper pair of caller stream st on the current device (created on first use); null on failure
+Helpers* helpers_for(hipStream_t st)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(g_helpers_mu);
+    Helpers& x = g_helpers[{dev, st}];
+    if (!x.start) {
+        bool ok = true;
+        for (int i = 0; i < 2 && ok; ++i)
+            ok = (x.s[i] || hipStreamCreateWithFlags(&x.s[i], hipStreamNonBlocking) == hipSuccess) &&
+                 (x.done[i] || hipEventCreateWithFlags(&x.done[i], hipEventDisableTiming) == hipSuccess);
+        if (!ok || hipEventCreateWithFlags(&x.start, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+    }
+    return &x;
+}
 
 constexpr double PI = 3.141592653589793238462643383279502884;
 constexpr size_t SCRATCH_MIN = size_t(1) << 30;   // jamp scratch per stream: at least 1 GiB,
@@ -638,7 +673,62 @@ int rambo_momenta(const me_handle* h, uint64_t seed, double sqrt_s, int64_t evt0
 
 namespace {
 
-// me_sigma, me_sigma_hel and me_sigma_select: equal chunks through the stream's scratch
+// scratch of `need` bytes for stream st (grown when too small); null on failure
+void* stream_scratch(me_handle* h, hipStream_t st, size_t need)
+{
+    std::lock_guard<std::mutex> lk(h->mu);
+    Scratch& s = h->scratch[st];
+    if (s.bytes < need) {
+        if (s.ptr) {
+            (void)hipStreamSynchronize(st);
+            (void)hipFree(s.ptr);
+            s.ptr = nullptr;
+            s.bytes = 0;
+        }
+        size_t want = std::max(need, std::min<size_t>(h->scratch_cap, 2 * s.bytes));
+        if (hipMalloc(&s.ptr, want) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        s.bytes = want;
+    }
+    return s.ptr;
+}
+
+// the plain |M|^2 in chunks that alternate between the two internal streams of the caller's
+// stream st; st waits for both at the end
+int sigma_piped(me_handle* h, const double* momenta, int64_t n_evt, double* out, const double* alphas,
+                hipStream_t st, int64_t chunk)
+{
+    Helpers* hp = helpers_for(st);
+    if (!hp) return fail(ME_EHIP, "creating the internal streams failed");
+    std::lock_guard<std::mutex> lk(hp->mu);
+    const size_t need = (size_t)chunk * h->bytes_per_event;
+    void* scr[2];
+    for (int i = 0; i < 2; ++i)
+        if (!(scr[i] = stream_scratch(h, hp->s[i], need))) return fail(ME_ENOMEM, "hipMalloc of the jamp scratch failed");
+    // the inputs are ready once the caller's stream reaches this point
+    if (hipEventRecord(hp->start, st) != hipSuccess) return fail(ME_EHIP, "event record failed");
+    for (int i = 0; i < 2; ++i) (void)hipStreamWaitEvent(hp->s[i], hp->start, 0);
+    const int npar = h->P->npar;
+    int64_t k = 0;
+    int rc = ME_OK;
+    for (int64_t c0 = 0; c0 < n_evt && rc == ME_OK; c0 += chunk, ++k) {
+        const int64_t nc = std::min(chunk, n_evt - c0);
+        const int i = (int)(k & 1);
+        rc = run_chunks(h, h->precision, h->d_hel_good, h->n_good, h->hel_per_group, h->groups, chunk,
+                        h->jamp_bytes_per_event, momenta + c0 * npar * 4, nc, out + c0, nullptr, scr[i], hp->s[i],
+                        h->profiling, nullptr, alphas ? alphas + c0 : nullptr);
+    }
+    // joined also after an error, so that no queued chunk outlives the caller's view of the call
+    for (int i = 0; i < 2; ++i) {
+        (void)hipEventRecord(hp->done[i], hp->s[i]);
+        (void)hipStreamWaitEvent(st, hp->done[i], 0);
+    }
+    return rc;
+}
+
+// me_sigma and its variants: equal chunks through the stream's scratch
 int sigma_impl(me_handle* h, const double* momenta, int64_t n_evt, double* out_me2, double* out_hel,
                const Selection* sel_in, void* stream, const double* alphas = nullptr, const int* chan = nullptr)
 {
@@ -655,34 +745,21 @@ int sigma_impl(me_handle* h, const double* momenta, int64_t n_evt, double* out_m
     if (chan && !h->P->sde_supported) return fail(ME_EINVAL, "no single-diagram channel weights for this process");
     if (reinterpret_cast<uintptr_t>(momenta) % 16 != 0) return fail(ME_EINVAL, "momenta must be 16-byte aligned");
     hipStream_t st = static_cast<hipStream_t>(stream);
+    // processes with segment kernels: chunks of half the size alternate between two internal
+    // streams (same scratch in total); the plain |M|^2 only
+    const bool piped = h->P->nslot > 0 && !sel_in && !out_hel && !chan && n_evt > h->chunk / 2;
+    const int64_t cap = piped ? std::max<int64_t>(64, h->chunk / 2 / 64 * 64) : h->chunk;
     // equal chunks no larger than the scratch cap allows
-    const int64_t n_chunks = (n_evt + h->chunk - 1) / h->chunk;
+    const int64_t n_chunks = (n_evt + cap - 1) / cap;
     const int64_t chunk = ((n_evt + n_chunks - 1) / n_chunks + 63) / 64 * 64;
+    if (piped) return sigma_piped(h, momenta, n_evt, out_me2, alphas, st, chunk);
     // selection adds |M_h|^2 and the leading-colour weights of one chunk
     const size_t sel_bytes = sel_in ? (size_t)(h->n_good + h->P->nc) * sizeof(double) : 0;
     // channel weights add two sums per (event, helicity)
     const size_t sde_bytes = chan ? (size_t)2 * h->n_good * sizeof(double) : 0;
     const size_t need = (size_t)chunk * (h->bytes_per_event + sel_bytes + sde_bytes);
-    void* scratch = nullptr;
-    {
-        std::lock_guard<std::mutex> lk(h->mu);
-        Scratch& s = h->scratch[st];
-        if (s.bytes < need) {
-            if (s.ptr) {
-                (void)hipStreamSynchronize(st);
-                (void)hipFree(s.ptr);
-                s.ptr = nullptr;
-                s.bytes = 0;
-            }
-            size_t want = std::max(need, std::min<size_t>(h->scratch_cap, 2 * s.bytes));
-            if (hipMalloc(&s.ptr, want) != hipSuccess) {
-                (void)hipGetLastError();
-                return fail(ME_ENOMEM, "hipMalloc of the jamp scratch failed");
-            }
-            s.bytes = want;
-        }
-        scratch = s.ptr;
-    }
+    void* scratch = stream_scratch(h, st, need);
+    if (!scratch) return fail(ME_ENOMEM, "hipMalloc of the jamp scratch failed");
     Selection sel{};
     if (sel_in) {
         sel = *sel_in;

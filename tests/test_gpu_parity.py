@@ -210,6 +210,31 @@ def test_large_batch_sampled_parity_ttggg():
     assert np.all(np.isfinite(got)) and np.all(got > 0)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed_fp16"])
+def test_ttggg_two_stream_chunks_equal_one_stream(precision):
+    """gg_ttggg's plain |M|^2 runs its half-size chunks on two internal streams; the call with
+    per-helicity output runs full chunks on the caller's stream.  Same helicity groups, so
+    bitwise the same |M|^2; on a caller stream of its own, work queued after the call sees
+    every chunk finished"""
+    name = "gg_ttggg"
+    proc = make_process(name, precision)
+    chunk = proc.info["chunk_events"]
+    n = 2 * chunk + 333
+    print(f"case two-stream chunks {name} {precision} n={n} chunk {chunk}", flush=True)
+    x = proc.rambo(21, W.sqrt_s(name), n)
+    one, _ = proc.sigma(x, per_helicity=True)
+    two = proc.sigma(x)
+    assert torch.equal(one, two) and bool(torch.all(one > 0))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        out = torch.zeros(n, dtype=torch.float64, device="cuda")
+        proc.sigma(x, out=out, stream=s)
+        later = out * 1.0   # queued on s behind the call
+    s.synchronize()
+    assert torch.equal(later, one)
+
+
 def test_empty_and_single_event():
     proc = make_process("gg_ttg")
     x = torch.empty((0, 5, 4), dtype=torch.float64, device="cuda")

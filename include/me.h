@@ -42,7 +42,8 @@ typedef struct me_handle me_handle; /* opaque, owned by the library */
 
 /* Create a handle for `process` (see the list above).
  * masses:    {m_t} or {m_t, w_t}; the top width must be 0 (no width in propagators).
- *            Ignored by ee_mumu and gg_gg.  NULL: m_t = 173.
+ *            m_t >= 0 (0: the massless-quark limit).  Ignored by ee_mumu and gg_gg.
+ *            NULL: m_t = 173.
  * couplings: {alpha_em, alpha_s}; NULL: {1/132.507, 0.118}.  Fixed couplings.
  * precision: ME_FP64 (all FP64), ME_MIXED_FP16 (FP32 wavefunctions and amplitudes,
  *            FP16 matrix-core colour sum with FP32 accumulation, FP64 momenta,

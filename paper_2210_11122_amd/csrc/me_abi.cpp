@@ -580,8 +580,8 @@ me_handle* me_create(const char* process, const double* masses, int n_masses, co
         h->alpha_em = couplings[0];
         h->alpha_s = couplings[1];
     }
-    if (!(h->mt > 0.0) || !(h->alpha_em > 0.0) || !(h->alpha_s > 0.0)) {
-        fail(ME_EINVAL, "masses and couplings must be positive");
+    if (!(h->mt >= 0.0) || !(h->alpha_em > 0.0) || !(h->alpha_s > 0.0)) {
+        fail(ME_EINVAL, "the top mass must be >= 0 and the couplings positive");
         delete h;
         return nullptr;
     }

@@ -14,6 +14,19 @@ Process ids and particle orders:
   gg_gg    (g, g, g, g)                       test process (pure gluon vertices)
   ee_mumu_z (e+, e-, mu+, mu-)                photon and Z exchange
 Parameters: params = (m_t, alpha_em, alpha_s).
+
+Pins (checks against what the physics fixes, never against this code's own formulas):
+  test_oracle_me.py         textbook |M|^2 of ee_mumu (photon, and photon + Z), gg_gg and gg_tt
+                            (Combridge) at several angles, the gg_tt threshold value and massless
+                            limit, brute-force explicit-colour sums,
+                            gauge, Lorentz and Bose invariance, basis independence;
+  test_oracle_parke_taylor.py  m_t = 0: vanishing helicities, Parke-Taylor moduli of every MHV
+                            amplitude of gg_tt .. gg_ttggg, the helicity-filter count;
+  test_oracle_soft_limit.py m_t = 173: eikonal factorisation gg_tt -> gg_ttg -> gg_ttgg -> gg_ttggg;
+  test_oracle_dirac_colour.py, test_oracle_rng_rambo.py, test_oracle_diagrams.py,
+  test_oracle_select.py     spinors, colour algebra, Philox and RAMBO, the diagram-by-diagram
+                            second algorithm, the selection draws.
+No function here is left "parity unpinned".
 """
 import ctypes
 import os

@@ -160,8 +160,10 @@ int me_helicity_ratios(const me_handle *h, double *out);
  * what was recorded since the previous call: total milliseconds and launch counts of the
  * amplitude kernel and of the colour-sum kernel (it waits for those events).  With the
  * fused colour sum (me_info_t.fused_colour) the amplitude figures include the colour
- * contraction and the colour-sum figures are those of the helicity-sum kernel.  Any
- * pointer may be NULL.  Not for use while another thread calls me_sigma on the same handle. */
+ * contraction and the colour-sum figures are those of the helicity-sum kernel.  On the
+ * two-stream path of me_sigma (gg_ttggg) the launches of the two internal streams overlap,
+ * so the totals can exceed the wall time.  Any pointer may be NULL.  Not for use while
+ * another thread calls me_sigma on the same handle. */
 int me_profile(me_handle *h, int enable, double *ms_amp, double *ms_colour, int64_t *n_amp,
                int64_t *n_colour);
 

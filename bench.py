@@ -262,6 +262,9 @@ def main():
         result["roofline"]["concurrent_streams"] = 2
         result["roofline"]["achieved_per_step_time"] = flops_kernel_step / (ms64 / 1e3) / 1e12
     tr = measured_traffic(name)
+    mean_launch = n_evt / max(amp_launches_per_step, 1)
+    if tr is not None and abs(tr.get("events_per_launch", 0) / mean_launch - 1) > 0.05:
+        tr = None   # counters taken at another launch size (the last launch of a batch may be short)
     if tr is not None:
         result["roofline"]["traffic"] = tr["hbm_bytes_per_launch"]
         result["roofline"]["traffic_source"] = tr["source"]

@@ -112,3 +112,34 @@ def test_massless_tops(name, n_evt):
         ok, r, spread = referee.judge(name, p[i], got[i], params)
         assert ok, (name, int(i), r, spread)
     assert np.all(np.isfinite(got)) and np.all(got > 0)
+
+
+@pytest.mark.parametrize("name,n_evt", [("gg_tt", 256), ("gg_ttg", 256), ("gg_ttgg", 128), ("gg_ttggg", 32)])
+def test_massless_mhv_helicities_closed_form(name, n_evt):
+    """m_t = 0: the GPU's colour-summed |M_h|^2 (me_sigma_hel) of every MHV and conjugate-MHV
+    helicity against the Parke-Taylor closed form (complex spinor products and the colour
+    matrix), event by event, on separated massless events"""
+    from paper_2210_11122_amd import Process
+    from tests.test_oracle_parke_taylor import mhv_colour_summed
+    n = W.n_par(name)
+    proc = Process(name, m_top=0.0, alpha_em=W.ALPHA_EM, alpha_s=W.ALPHA_S)
+    print(f"case massless MHV closed form {name} n={n_evt}", flush=True)
+    p = oracle.rambo(29, W.sqrt_s(name), [0.0] * (n - 2), 4 * n_evt)
+    out = p.copy()
+    out[:, :2] *= -1
+    dots = out[:, :, None, 0] * out[:, None, :, 0] - np.einsum("eik,ejk->eij", out[:, :, 1:], out[:, :, 1:])
+    iu = np.triu_indices(n, 1)
+    keep = np.abs(2 * dots[:, iu[0], iu[1]]).min(axis=1) >= 1e-3 * W.sqrt_s(name) ** 2
+    p = np.ascontiguousarray(p[keep][:n_evt])
+    assert p.shape[0] == n_evt
+    _, hel = proc.sigma(torch.from_numpy(p).cuda(), per_helicity=True)
+    hel = hel.cpu().numpy()
+    col = {h: k for k, h in enumerate(proc.good_helicities_index())}
+    C = oracle.colour_matrix(name)
+    checked = 0
+    for e in range(n_evt):
+        for h, want in mhv_colour_summed(name, p[e], C).items():
+            assert h in col, (name, h)          # every MHV helicity survives the filter
+            assert abs(hel[e, col[h]] / want - 1) <= 1e-11, (name, e, h, hel[e, col[h]], want)
+            checked += 1
+    assert checked == n_evt * (2 * (n - 2) if n == 4 else 4 * (n - 2))

@@ -119,3 +119,58 @@ def test_helicity_filter_keeps_the_non_vanishing_configurations(proc):
             want.append(h)
     assert len(want) == 2 * (2 ** (n - 2) - 2)
     assert sorted(int(h) for h in good) == want
+
+
+def _angle(p, q):
+    """spinor product <p q> of two positive-energy massless momenta (one fixed phase convention;
+    every particle's phase appears once in each cyclic product below, so ratios do not depend on it)"""
+    pp, pm = p[0] + p[3], p[0] - p[3]
+    qp, qm = q[0] + q[3], q[0] - q[3]
+    ep = (p[1] + 1j * p[2]) / math.sqrt(pp * pm) if pp * pm > 0 else 1.0
+    eq = (q[1] + 1j * q[2]) / math.sqrt(qp * qm) if qp * qm > 0 else 1.0
+    return math.sqrt(pm * qp) * ep - math.sqrt(pp * qm) * eq
+
+
+def mhv_colour_summed(proc, ev, colour):
+    """{helicity index: colour-summed |M_h|^2} of every MHV and conjugate-MHV helicity at m_t = 0:
+    A_sigma = c N / P_sigma with P_sigma the cyclic product of <a b> along (t, gluons of sigma, t~)
+    and |c| = (sqrt(2) g_s)^(n-2), |N|^2 = s_fj^3 s_f'j, so
+    |M_h|^2 = (2 g_s^2)^(n-2) |N|^2 sum_{sigma,sigma'} conj(1/P_sigma) C_{sigma sigma'} (1/P_sigma');
+    the conjugate amplitudes give the complex conjugate sum, the same real number.  Crossing an
+    incoming momentum multiplies its spinors by a phase, which cancels in every ratio."""
+    n = len(ev)
+    g_s = math.sqrt(4 * math.pi * W.ALPHA_S)
+    glu = [0, 1] + list(range(4, n))
+    chains = [[2] + [glu[g] for g in o] + [3] for o in oracle.orderings(proc)]
+    v = 1.0 / np.array([np.prod([_angle(ev[c[k]], ev[c[(k + 1) % n]]) for k in range(n)]) for c in chains])
+    colour_sum = float(np.real(np.conj(v) @ colour @ v))
+    s = _mandelstam(_outgoing(ev))
+    out = {}
+    for h in range(1 << n):
+        lam = [2 * ((h >> (n - 1 - i)) & 1) - 1 for i in range(n)]
+        lam_out = [-lam[0], -lam[1]] + lam[2:]
+        neg = [i for i in range(n) if lam_out[i] < 0]
+        pos = [i for i in range(n) if lam_out[i] > 0]
+        if lam_out[2] == lam_out[3]:
+            continue
+        odd = neg if len(neg) == 2 else (pos if len(pos) == 2 else None)
+        if odd is None:
+            continue
+        f = 2 if 2 in odd else 3
+        j = odd[0] if odd[1] == f else odd[1]
+        out[h] = (2 * g_s ** 2) ** (n - 2) * s(f, j) ** 3 * s(5 - f, j) * colour_sum
+    return out
+
+
+@pytest.mark.parametrize("proc", ["gg_tt", "gg_ttg", "gg_ttgg", "gg_ttggg"])
+def test_mhv_colour_summed_closed_form(proc):
+    """the colour-summed |M_h|^2 of every MHV helicity equals the Parke-Taylor closed form with
+    complex spinor products and the colour matrix"""
+    n = W.n_par(proc)
+    C = oracle.colour_matrix(proc)
+    for ev in _events(proc, 4, 2):
+        _, hel = oracle.me(proc, ev, params=PARAMS_MASSLESS, per_helicity=True)
+        want = mhv_colour_summed(proc, ev, C)
+        assert len(want) == (2 * (n - 2) if n == 4 else 4 * (n - 2))
+        for h, v in want.items():
+            assert abs(hel[h] / v - 1) <= 1e-12, (proc, h, hel[h], v)

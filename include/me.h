@@ -71,8 +71,8 @@ int rambo_momenta(const me_handle *h, uint64_t seed, double sqrt_s, int64_t evt0
  * misalignment or n_evt < 0.  Unphysical momenta are not checked (they give NaN/inf).
  * Work is split into chunks that bound the handle's per-stream scratch; calls on
  * different streams may overlap.  For processes with segment kernels (gg_ttggg) and
- * batches above half a chunk, half-size chunks alternate between two internal streams
- * of the caller's stream (default priority; one pair per device and caller stream, shared
+ * batches of more than one chunk, the chunks alternate between two internal streams, each
+ * with its own scratch (twice the per-stream scratch), of the caller's stream (default priority; one pair per device and caller stream, shared
  * by all handles, created on first use and kept until the process ends); they start
  * after the work queued on `stream` before the call, and `stream` waits for both, so work
  * queued on `stream` after the call sees the finished output. */

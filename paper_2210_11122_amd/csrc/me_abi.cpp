@@ -745,10 +745,12 @@ int sigma_impl(me_handle* h, const double* momenta, int64_t n_evt, double* out_m
     if (chan && !h->P->sde_supported) return fail(ME_EINVAL, "no single-diagram channel weights for this process");
     if (reinterpret_cast<uintptr_t>(momenta) % 16 != 0) return fail(ME_EINVAL, "momenta must be 16-byte aligned");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    // processes with segment kernels: chunks of half the size alternate between two internal
-    // streams (same scratch in total); the plain |M|^2 only
-    const bool piped = h->P->nslot > 0 && !sel_in && !out_hel && !chan && n_evt > h->chunk / 2;
-    const int64_t cap = piped ? std::max<int64_t>(64, h->chunk / 2 / 64 * 64) : h->chunk;
+    // processes with segment kernels, batches of more than one chunk: the chunks alternate
+    // between two internal streams, each with a scratch buffer of its own (twice the scratch;
+    // full-size chunks keep the short segment launches several rounds of waves deep); the plain
+    // |M|^2 only
+    const bool piped = h->P->nslot > 0 && !sel_in && !out_hel && !chan && n_evt > h->chunk;
+    const int64_t cap = h->chunk;
     // equal chunks no larger than the scratch cap allows
     const int64_t n_chunks = (n_evt + cap - 1) / cap;
     const int64_t chunk = ((n_evt + n_chunks - 1) / n_chunks + 63) / 64 * 64;

@@ -212,8 +212,8 @@ def test_large_batch_sampled_parity_ttggg():
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed_fp16"])
 def test_ttggg_two_stream_chunks_equal_one_stream(precision):
-    """gg_ttggg's plain |M|^2 runs its half-size chunks on two internal streams; the call with
-    per-helicity output runs full chunks on the caller's stream.  Same helicity groups, so
+    """gg_ttggg's plain |M|^2 runs its chunks on two internal streams; the call with
+    per-helicity output runs them on the caller's stream.  Same helicity groups, so
     bitwise the same |M|^2; on a caller stream of its own, work queued after the call sees
     every chunk finished"""
     name = "gg_ttggg"

@@ -212,6 +212,8 @@ class GpuExecutor:
         mom = req.n_evt * info["n_par"] * 32
         out = req.n_evt * 8
         scratch = min(req.n_evt + 63, info["chunk_events"]) * info["bytes_per_event_scratch"]
+        if info["n_partial_slots"] > 0 and req.n_evt > info["chunk_events"]:
+            scratch *= 2   # the library's two internal streams, a chunk of scratch each
         return mom + out + scratch
 
     def launch(self, req, slot):

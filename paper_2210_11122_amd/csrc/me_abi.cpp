@@ -709,7 +709,9 @@ int sigma_piped(me_handle* h, const double* momenta, int64_t n_evt, double* out,
         if (!(scr[i] = stream_scratch(h, hp->s[i], need))) return fail(ME_ENOMEM, "hipMalloc of the jamp scratch failed");
     // the inputs are ready once the caller's stream reaches this point
     if (hipEventRecord(hp->start, st) != hipSuccess) return fail(ME_EHIP, "event record failed");
-    for (int i = 0; i < 2; ++i) (void)hipStreamWaitEvent(hp->s[i], hp->start, 0);
+    for (int i = 0; i < 2; ++i)
+        if (hipStreamWaitEvent(hp->s[i], hp->start, 0) != hipSuccess)
+            return fail(ME_EHIP, "ordering the internal streams after the caller's stream failed");
     const int npar = h->P->npar;
     int64_t k = 0;
     int rc = ME_OK;
@@ -722,8 +724,9 @@ int sigma_piped(me_handle* h, const double* momenta, int64_t n_evt, double* out,
     }
     // joined also after an error, so that no queued chunk outlives the caller's view of the call
     for (int i = 0; i < 2; ++i) {
-        (void)hipEventRecord(hp->done[i], hp->s[i]);
-        (void)hipStreamWaitEvent(st, hp->done[i], 0);
+        const bool joined = hipEventRecord(hp->done[i], hp->s[i]) == hipSuccess &&
+                            hipStreamWaitEvent(st, hp->done[i], 0) == hipSuccess;
+        if (!joined && rc == ME_OK) rc = fail(ME_EHIP, "joining the internal streams to the caller's stream failed");
     }
     return rc;
 }

@@ -29,6 +29,7 @@
  */
 #ifndef ME_H
 #define ME_H
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -77,6 +78,24 @@ int rambo_momenta(const me_handle *h, uint64_t seed, double sqrt_s, int64_t evt0
  * after the work queued on `stream` before the call, and `stream` waits for both, so work
  * queued on `stream` after the call sees the finished output. */
 int me_sigma(me_handle *h, const double *momenta, int64_t n_evt, double *out_me2, void *stream);
+
+/* me_sigma for callers that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same arguments, same results: every event's
+ * out_me2 is bitwise that of me_sigma on the same handle.  It calls no hipMalloc, hipFree or other
+ * allocating routine.  Its scratch is a static device array of ME_NOALLOC_SCRATCH_BYTES (256 MiB)
+ * that belongs to the library: one per GPU, held from the library's first use on that GPU until
+ * the process ends.  Its address is resolved when a handle is created on the GPU (or at the
+ * first call there).  The batch runs on `stream` alone, with no internal streams, in chunks of at
+ * most the handle's chunk_events (me_info) that fit the array; no kernel reads a part of the
+ * array that the same call has not written, so nothing needs clearing between calls.
+ * Every call on one GPU shares that GPU's array, whichever handle or stream it uses, and the
+ * array keeps the last call's contents: calls that overlap in time on one GPU (other host
+ * threads, or other streams whose work has not completed) race and give wrong results.
+ * Errors as me_sigma; ME_ENOMEM if one 64-event chunk of the handle's process and precision needs
+ * more scratch than the array holds (none of the processes in the list above does), ME_EHIP if
+ * the array's device address cannot be resolved. */
+#define ME_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int me_sigma_noalloc(me_handle *h, const double *momenta, int64_t n_evt, double *out_me2, void *stream);
 
 /* As me_sigma, and also out_hel[e * n_good + k] = colour-summed |M_h|^2 (not averaged) of
  * the k-th good helicity of event e (DEVICE double[n_evt][n_good], may be NULL). */

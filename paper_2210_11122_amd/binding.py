@@ -36,7 +36,7 @@ class MeInfo(ctypes.Structure):
 
 
 EXPORTS = ["me_create", "me_destroy", "me_info", "me_last_error", "rambo_momenta", "me_sigma",
-           "me_sigma_hel", "me_sigma_select", "me_sigma_alphas", "me_sigma_channel", "me_diagrams", "me_colour_flows", "me_good_helicities", "me_helicity_ratios",
+           "me_sigma_noalloc", "me_sigma_hel", "me_sigma_select", "me_sigma_alphas", "me_sigma_channel", "me_diagrams", "me_colour_flows", "me_good_helicities", "me_helicity_ratios",
            "me_profile", "me_set_option"]
 
 _lib = None
@@ -58,6 +58,7 @@ def load():
     L.me_last_error.restype = ctypes.c_char_p
     L.rambo_momenta.argtypes = [vp, ctypes.c_uint64, ctypes.c_double, ctypes.c_int64, ctypes.c_int64, vp, vp]
     L.me_sigma.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
+    L.me_sigma_noalloc.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
     L.me_sigma_hel.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp]
     L.me_sigma_select.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp, vp, vp, vp]
     L.me_colour_flows.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
@@ -143,6 +144,18 @@ class Process:
             return out, hel
         _check(load().me_sigma(self._h, ctypes.c_void_p(momenta.data_ptr()), n, ctypes.c_void_p(out.data_ptr()),
                                _stream_ptr(stream)), "me_sigma")
+        return out
+
+    def sigma_noalloc(self, momenta, out, stream=None):
+        """me_sigma_noalloc: as sigma, with the library's static scratch (allocates nothing;
+        out must be given)"""
+        import torch
+        assert momenta.is_cuda and momenta.dtype == torch.float64 and momenta.is_contiguous()
+        n = momenta.shape[0]
+        assert momenta.shape[1:] == (self.n_par, 4)
+        assert out.is_cuda and out.dtype == torch.float64 and out.is_contiguous() and out.shape == (n,)
+        _check(load().me_sigma_noalloc(self._h, ctypes.c_void_p(momenta.data_ptr()), n,
+                                       ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)), "me_sigma_noalloc")
         return out
 
     def select(self, momenta, r_hel, r_col, stream=None):

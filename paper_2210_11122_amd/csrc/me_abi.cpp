@@ -81,6 +81,36 @@ Helpers* helpers_for(hipStream_t st)
     return &x;
 }
 
+// Scratch of me_sigma_noalloc: one array per GPU, part of the library's code object, so it is
+// allocated when the library is loaded onto a device and held until the process ends.  In host
+// code its name is only a stand-in for the symbol: the device address comes from
+// hipGetSymbolAddress, per device (each GPU holds its own copy at its own address).
+static __device__ __align__(256) unsigned char static_scratch[ME_NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[MAX_DEVICES] = {};
+
+// device address of the current device's static scratch (resolved once per device); null on failure
+void* static_scratch_ptr()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(static_scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_static_ptr[dev] = p;
+    }
+    return g_static_ptr[dev];
+}
+
 constexpr double PI = 3.141592653589793238462643383279502884;
 constexpr size_t SCRATCH_MIN = size_t(1) << 30;   // jamp scratch per stream: at least 1 GiB,
 constexpr int64_t SCRATCH_EVENTS = 4096;          // room for 4096 events, at most 1/8 of the device
@@ -586,6 +616,9 @@ me_handle* me_create(const char* process, const double* masses, int n_masses, co
         return nullptr;
     }
     h->g = std::sqrt(4.0 * PI * (P->coupling ? h->alpha_s : h->alpha_em));
+    // set-up of me_sigma_noalloc: the device address of this GPU's static scratch (a failure
+    // here is reported by that entry point, which tries again)
+    (void)static_scratch_ptr();
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (upload_colour(h) != ME_OK || helicity_prepass(h, st) != ME_OK) {
         std::string msg = g_err;
@@ -856,6 +889,36 @@ int me_profile(me_handle* h, int enable, double* ms_amp, double* ms_colour, int6
 int me_sigma(me_handle* h, const double* momenta, int64_t n_evt, double* out_me2, void* stream)
 {
     return me_sigma_hel(h, momenta, n_evt, out_me2, nullptr, stream);
+}
+
+int me_sigma_noalloc(me_handle* h, const double* momenta, int64_t n_evt, double* out_me2, void* stream)
+{
+    if (!h) return fail(ME_EINVAL, "handle is NULL");
+    if (n_evt < 0) return fail(ME_EINVAL, "negative event count");
+    if (n_evt == 0) return ME_OK;
+    if (!is_device_pointer(momenta) || !is_device_pointer(out_me2))
+        return fail(ME_EINVAL, "momenta and out_me2 must be device pointers");
+    if (reinterpret_cast<uintptr_t>(momenta) % 16 != 0) return fail(ME_EINVAL, "momenta must be 16-byte aligned");
+    void* scr = static_scratch_ptr();
+    if (!scr) return fail(ME_EHIP, "hipGetSymbolAddress of the static scratch failed");
+    const me::ProcessDesc* P = h->P;
+    // scratch per event: D |M_h|^2 per good helicity where the amplitude kernel does the colour sum,
+    // else the jamps (and partial slots) of every good helicity plus the helicity-group sums
+    const bool fused = P->fused_colour && h->fuse_colour;
+    const size_t per_event = fused ? (size_t)h->n_good * sizeof(double) : h->bytes_per_event;
+    const int64_t fit = (int64_t)(ME_NOALLOC_SCRATCH_BYTES / per_event) / 64 * 64;
+    if (fit < 64)
+        return fail(ME_ENOMEM, std::string("me_sigma_noalloc: ") + P->name + " needs " +
+                                   std::to_string(64 * per_event) + " bytes of scratch for one 64-event chunk; the "
+                                   "static scratch holds " + std::to_string((size_t)ME_NOALLOC_SCRATCH_BYTES));
+    // the handle's own chunk where it fits (the launches of me_sigma), else the largest that does;
+    // the helicity groups are the handle's, so every event's result is bitwise that of me_sigma
+    const int64_t cap = std::min<int64_t>(h->chunk, fit);
+    const int64_t n_chunks = (n_evt + cap - 1) / cap;
+    const int64_t chunk = ((n_evt + n_chunks - 1) / n_chunks + 63) / 64 * 64;
+    const size_t jamp_per_event = fused ? per_event : h->jamp_bytes_per_event;
+    return run_chunks(h, h->precision, h->d_hel_good, h->n_good, h->hel_per_group, h->groups, chunk, jamp_per_event,
+                      momenta, n_evt, out_me2, nullptr, scr, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

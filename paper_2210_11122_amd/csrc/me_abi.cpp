@@ -430,12 +430,13 @@ int run_chunks(me_handle* h, int precision, const signed char* hel, int n_good, 
 void free_handle(me_handle* h)
 {
     if (!h) return;
-    for (auto& kv : h->scratch) {
-        if (kv.second.ptr) {
-            (void)hipStreamSynchronize(kv.first);
-            (void)hipFree(kv.second.ptr);
-        }
-    }
+    // the caller's streams may be gone by now: wait for the whole device before freeing the
+    // scratch that queued work may still use
+    bool any = false;
+    for (auto& kv : h->scratch) any |= kv.second.ptr != nullptr;
+    if (any) (void)hipDeviceSynchronize();
+    for (auto& kv : h->scratch)
+        if (kv.second.ptr) (void)hipFree(kv.second.ptr);
     for (auto& m : h->marks) {
         (void)hipEventDestroy(m.a);
         (void)hipEventDestroy(m.b);

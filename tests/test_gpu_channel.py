@@ -43,6 +43,43 @@ def test_channel_weights_match_oracle(name, n_evt, n_chan):
             assert got[e, k] == pytest.approx(want, rel=1e-12), (e, int(c))
 
 
+def test_channel_weights_ttggg_match_oracle():
+    """gg_ttggg: the weights of 24 channels of two events against the oracle's W_d.  The
+    oracle's colour weights K_ds and its helicity filter take about a minute, so they come
+    from tests/golden/gg_ttggg_channel_tables.json (written by the script beside it, which
+    calls only the oracle); a sample of K_ds is recomputed here."""
+    import json
+    import os
+    name = "gg_ttggg"
+    print(f"case channel weights {name} vs oracle", flush=True)
+    tab = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "gg_ttggg_channel_tables.json")))
+    ents = Dg.entries(name)
+    assert [tuple(e["lines"]) for e in tab["entries"]] == [Dg.descriptor(name, d) for d, _ in ents]
+    assert [tuple(e["assign"]) for e in tab["entries"]] == [tuple(s) for _, s in ents]
+    K = np.array([e["K"] for e in tab["entries"]])
+    for i in range(0, len(ents), 97):
+        d, s = ents[i]
+        assert np.sum(np.abs(Dg.colour_tensor(d, s, 5)) ** 2) == pytest.approx(K[i], rel=1e-13)
+    good = tab["good_helicities"]
+    proc = make_process(name)
+    lines = proc.diagrams()
+    assert set(lines) == {Dg.descriptor(name, d) for d, _ in ents}
+    assert sorted(proc.good_helicities_index()) == good
+    p = oracle.rambo(45, W.sqrt_s(name), W.final_masses(name), 2)
+    me = proc.sigma(torch.from_numpy(p).cuda()).cpu().numpy()
+    for e in range(2):
+        Wd = Dg.diagram_weights(name, p[e], W.PARAMS, K, helicities=good)
+        tot = sum(Wd.values())
+        # spread over the numbering, plus the event's three largest channels
+        top = sorted(range(len(lines)), key=lambda c: -Wd[lines[c]])[:3]
+        chans = np.array(sorted(set(np.linspace(0, len(lines) - 1, 21).astype(int)) | set(top)), dtype=np.int32)
+        x = torch.from_numpy(np.repeat(p[e:e + 1], len(chans), axis=0)).cuda()
+        got = proc.sigma_channel(x, torch.from_numpy(chans).cuda()).cpu().numpy()
+        for k, c in enumerate(chans):
+            want = me[e] * Wd[lines[c]] / tot
+            assert got[k] == pytest.approx(want, rel=1e-12), (e, int(c))
+
+
 def test_channel_weights_sum_to_one_and_no_channel():
     name = "gg_ttgg"
     proc = make_process(name)

@@ -51,6 +51,29 @@ def test_fp64_matches_oracle(name, n):
     check_fp64(name, p, got)
 
 
+@pytest.mark.parametrize("name", ["gg_tt", "gg_ttg"])
+def test_fp64_full_configured_batch_matches_oracle(name):
+    """every event of the configured batch (gg_tt 2^19, gg_ttg 2^20 events of seed 0) against the
+    oracle, with the referee for events beyond 1e-12"""
+    from tests import hostinfo
+    n = W.PROCESSES[name][2]
+    threads = min(16, hostinfo.host_threads())
+    print(f"case fp64 full batch {name} n={n} oracle threads={threads}", flush=True)
+    p = oracle.rambo(W.SEED, W.sqrt_s(name), W.final_masses(name), n)
+    proc = make_process(name)
+    got = proc.sigma(torch.from_numpy(p).cuda()).cpu().numpy()
+    want = oracle.me_batch(name, p, params=W.PARAMS, threads=threads)
+    rel = np.abs(got / want - 1)
+    bad = np.where(rel > TOL)[0]
+    worst = []
+    for i in bad:
+        ok, r, spread = referee.judge(name, p[i], got[i], W.PARAMS)
+        worst.append((r, spread, int(i)))
+        assert ok, (name, int(i), float(got[i]), float(want[i]), r, spread)
+    print(f"{name}: {n} events, max rel {rel.max():.2e}, median {np.median(rel):.2e}, beyond 1e-12: {len(bad)} "
+          f"(all within their FP64 conditioning; worst {sorted(worst, reverse=True)[:2]})", flush=True)
+
+
 @pytest.mark.parametrize("name", ["gg_tt", "gg_ttg", "gg_ttgg", "gg_ttggg"])
 def test_per_helicity_matches_oracle(name):
     print(f"case per-helicity {name}", flush=True)
@@ -85,19 +108,47 @@ def test_filtered_equals_unfiltered_oracle_on_held_out_events(name):
     assert np.max(np.abs(got / want - 1)) <= TOL
 
 
+def rambo_boost_gamma(seed, n_final, evt0, n):
+    """gamma of RAMBO's conformal boost for each event, from the event's own uniforms: the
+    raw massless vectors q_i (energy -ln(r3 r4), direction from r1, r2) sum to Q, and
+    gamma = Q^0 / sqrt(Q^2)"""
+    Q = np.zeros((n, 4))
+    for e in range(n):
+        for i in range(n_final):
+            r = oracle.uniforms(seed, evt0 + e, n_final, i)
+            c = 2.0 * r[0] - 1.0
+            s = np.sqrt(1.0 - c * c)
+            q0 = -np.log(r[2] * r[3])
+            Q[e] += q0 * np.array([1.0, s * np.cos(2 * np.pi * r[1]), s * np.sin(2 * np.pi * r[1]), c])
+    return Q[:, 0] / np.sqrt(Q[:, 0] ** 2 - (Q[:, 1:] ** 2).sum(axis=1))
+
+
+def rambo_bound(seed, n_final, evt0, n, rs):
+    """Per-event bound on |GPU - CPU| for identical random numbers.  The GPU's sin, cos and log
+    may differ from glibc's in the last bits.  The boost's scale sqrt(s)/M and its direction
+    come from M^2 = Q0^2 - |Q|^2, which cancels to relative size 1/gamma^2, so a relative
+    difference eps in the raw vectors moves the momenta by about eps gamma^2 sqrt(s).  With
+    +-2-ulp perturbations of those values the deviation stays below 8 eps gamma^2 sqrt(s) per
+    event (simulated on the CPU for every process); the bound allows 64."""
+    g = rambo_boost_gamma(seed, n_final, evt0, n)
+    return 64 * 2.0 ** -53 * g * g * rs
+
+
 @pytest.mark.parametrize("name", W.ALL)
 def test_rambo_gpu_matches_cpu(name):
     proc = make_process(name)
     n = 4099
     rs = W.sqrt_s(name)
+    nf = len(W.final_masses(name))
     for seed in (0, 77):
         g = proc.rambo(seed, rs, n).cpu().numpy()
         c = oracle.rambo(seed, rs, W.final_masses(name), n)
         d = np.max(np.abs(g - c), axis=(1, 2))
-        # identical random numbers; sin/cos/log differ in the last bit between the GPU and
-        # glibc, and the conformal boost amplifies that by its gamma factor, which is large
-        # for nearly collinear raw vectors (mostly two-body events): bound the tail
-        assert np.quantile(d, 0.99) <= 1e-13 * rs and d.max() <= 1e-9 * rs
+        bound = rambo_bound(seed, nf, 0, n, rs)
+        worst = int(np.argmax(d / bound))
+        print(f"rambo {name} seed {seed}: max |d| {d.max():.2e}, worst d/bound {d[worst] / bound[worst]:.3f} "
+              f"(gamma^2 {bound[worst] / (64 * 2.0 ** -53 * rs):.1f})", flush=True)
+        assert np.all(d <= bound), (name, seed, worst, d[worst], bound[worst])
         # the GPU points are themselves exact phase-space points
         tot = g[:, 2:].sum(axis=1) - g[:, :2].sum(axis=1)
         assert np.max(np.abs(tot)) <= 1e-12 * rs
@@ -106,7 +157,7 @@ def test_rambo_gpu_matches_cpu(name):
             assert np.max(np.abs(q[:, 0] ** 2 - (q[:, 1:] ** 2).sum(axis=1) - m * m)) <= 1e-12 * rs * rs
     g = proc.rambo(5, W.sqrt_s(name), 100, evt0=1000).cpu().numpy()
     c = oracle.rambo(5, W.sqrt_s(name), W.final_masses(name), 100, evt0=1000)
-    assert np.max(np.abs(g - c)) <= 1e-13 * W.sqrt_s(name)
+    assert np.all(np.max(np.abs(g - c), axis=(1, 2)) <= rambo_bound(5, nf, 1000, 100, rs))
 
 
 # Mixed-form bars.  Both forms run the amplitudes in FP32 (unit roundoff 6e-8) and split each

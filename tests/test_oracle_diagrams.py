@@ -75,3 +75,22 @@ def test_diagram_jamps_equal_berends_giele_partials(name):
         A = oracle.partials(name, p, h, params=W.PARAMS)
         assert np.max(np.abs(J - A)) <= 1e-12 * scale
     assert Dg.diagram_me(name, p, W.PARAMS) == pytest.approx(oracle.me(name, p, params=W.PARAMS), rel=1e-12)
+
+
+def test_golden_gg_ttggg_channel_tables_match_oracle():
+    """tests/golden/gg_ttggg_channel_tables.json (the oracle's gg_ttggg colour weights and
+    helicity filter, precomputed by the script beside it) against the oracle: entry order and
+    internal lines, a sample of K_ds, and the filter's outcome at m_t = 173 GeV (massive tops:
+    no helicity combination vanishes identically, so all 128 are kept)"""
+    import json
+    import os
+    name = "gg_ttggg"
+    tab = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "gg_ttggg_channel_tables.json")))
+    ents = Dg.entries(name)
+    assert len(ents) == len(tab["entries"]) == 1890
+    assert [tuple(e["lines"]) for e in tab["entries"]] == [Dg.descriptor(name, d) for d, _ in ents]
+    assert [tuple(e["assign"]) for e in tab["entries"]] == [tuple(s) for _, s in ents]
+    for i in range(0, len(ents), 61):
+        d, s = ents[i]
+        assert np.sum(np.abs(Dg.colour_tensor(d, s, 5)) ** 2) == pytest.approx(tab["entries"][i]["K"], rel=1e-13)
+    assert tab["good_helicities"] == list(range(128))

@@ -151,6 +151,118 @@ def cpu_baseline(name, n_evt_total, params, budget_s, threads):
     return p, me, n / dt, dt
 
 
+# oracle subset per process for the table: enough events for the error statistics, a few
+# seconds of the oracle on the host threads
+TABLE_ORACLE_EVENTS = {"ee_mumu": 8192, "gg_tt": 65536, "gg_ttg": 16384, "gg_ttgg": 4096, "gg_ttggg": 1024}
+
+
+def rel_stats(rel):
+    import numpy as np
+    return {"max": float(rel.max()), "median": float(np.median(rel)), "p99": float(np.quantile(rel, 0.99)),
+            "p999": float(np.quantile(rel, 0.999)), "n": int(rel.size)}
+
+
+def process_table(torch, min_ms=500.0, threads=None):
+    """Per process at its configured size: MEs/s of the FP64 and the two mixed forms (median
+    per-call time), the amplitude kernel's algorithmic rate against the VALU peak (HIP events
+    around its launches), the end-to-end rate (MEs/s x algorithmic flops per ME), the mixed
+    forms' relative error against the GPU FP64 result on the whole batch and against the FP64
+    oracle on a subset, and the oracle's own MEs/s on all host threads and on one."""
+    import numpy as np
+    import oracle
+    from paper_2210_11122_amd import Process
+    from tests import hostinfo
+    from tests import workloads as W
+    threads = threads or hostinfo.host_threads()
+    rows = []
+    for name in W.ALL:
+        n = W.PROCESSES[name][2]
+        rs = W.sqrt_s(name)
+        row = {"process": name, "n_events": n}
+        ref = None
+        nsub = min(n, TABLE_ORACLE_EVENTS[name])
+        psub = oracle.rambo(W.SEED, rs, W.final_masses(name), nsub)
+        t = time.perf_counter()
+        me_or = oracle.me_batch(name, psub, params=W.PARAMS, threads=threads)
+        dt = time.perf_counter() - t
+        row["oracle"] = {"MEs_per_s": nsub / dt, "threads": threads, "events": nsub}
+        n1 = max(1, min(nsub, int(nsub / dt / threads * 1.5)))
+        t = time.perf_counter()
+        oracle.me_batch(name, psub[:n1], params=W.PARAMS, threads=1)
+        row["oracle"]["MEs_per_s_single_thread"] = n1 / (time.perf_counter() - t)
+        xsub = torch.from_numpy(psub).cuda()
+        for prec in ("fp64", "mixed_fp16", "mixed_bf16"):
+            proc = Process(name, m_top=W.M_TOP, alpha_em=W.ALPHA_EM, alpha_s=W.ALPHA_S, precision=prec)
+            info = proc.info
+            x = proc.rambo(W.SEED, rs, n)
+            y = torch.empty(n, dtype=torch.float64, device="cuda")
+            for _ in range(2):
+                proc.sigma(x, out=y)
+            torch.cuda.synchronize()
+            proc.profile(True)
+            times, spent = [], 0.0
+            while len(times) < 5 or (spent < min_ms and len(times) < 200):
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record()
+                proc.sigma(x, out=y)
+                b.record()
+                b.synchronize()
+                times.append(a.elapsed_time(b))
+                spent += times[-1]
+            ms_amp, ms_cs, n_amp, _ = proc.profile(False)
+            med = float(np.median(times))
+            lanes = n * info["n_good_hel"]
+            f_amp = info["flops_amp_lane"] + (info["flops_colour_lane"] if info["fused_colour"] else 0.0)
+            f_me = info["n_good_hel"] * (info["flops_amp_lane"] + info["flops_colour_lane"])
+            mes = n / med * 1e3
+            r = {"MEs_per_s": mes, "ms_per_call": med, "calls": len(times),
+                 "amp_kernel_tflops": f_amp * lanes * len(times) / (ms_amp / 1e3) / 1e12 if ms_amp > 0 else None,
+                 "end_to_end_tflops": mes * f_me / 1e12,
+                 "flops_per_me": f_me, "colour_sum_in_amp_kernel": bool(info["fused_colour"]),
+                 "two_streams": bool(info["n_partial_slots"] > 0 and n > info["chunk_events"])}
+            r["amp_kernel_frac"] = r["amp_kernel_tflops"] / FP64_VALU_PEAK_TFLOPS if r["amp_kernel_tflops"] else None
+            r["end_to_end_frac"] = r["end_to_end_tflops"] / FP64_VALU_PEAK_TFLOPS
+            got_sub = proc.sigma(xsub).cpu().numpy()
+            rel_or = np.abs(got_sub / me_or - 1)
+            r["rel_err_vs_oracle"] = rel_stats(rel_or)
+            if prec == "fp64":
+                ref = y.clone()
+                r["n_over_1e-12_vs_oracle"] = int((rel_or > 1e-12).sum())
+            else:
+                r["rel_err_vs_gpu_fp64_full_batch"] = rel_stats((y / ref - 1).abs().cpu().numpy())
+            row[prec] = r
+            log(f"table {name} {prec}: {mes:.4g} MEs/s, amp kernel {r['amp_kernel_tflops'] or 0:.2f} TFLOP/s, "
+                f"vs oracle max {rel_or.max():.2e} median {np.median(rel_or):.2e}")
+            del proc, x, y
+        rows.append(row)
+    return rows
+
+
+def table_markdown(rows):
+    def f(v, k=3):
+        return "-" if v is None else f"{v:.{k}g}"
+    L = ["| process | events | form | MEs/s | amp. kernel TFLOP/s (frac of 78.6) | end-to-end frac | "
+         "rel. err vs FP64 oracle (max / median / p99 / p99.9; n) | vs GPU FP64, full batch (max / median) |",
+         "|---|---|---|---|---|---|---|---|"]
+    for row in rows:
+        for prec in ("fp64", "mixed_fp16", "mixed_bf16"):
+            r = row[prec]
+            e = r["rel_err_vs_oracle"]
+            g = r.get("rel_err_vs_gpu_fp64_full_batch")
+            L.append(f"| {row['process']} | {row['n_events']} | {prec} | {f(r['MEs_per_s'], 4)} | "
+                     f"{f(r['amp_kernel_tflops'])} ({f(r['amp_kernel_frac'], 2)}) | {f(r['end_to_end_frac'], 2)} | "
+                     f"{f(e['max'], 2)} / {f(e['median'], 2)} / {f(e['p99'], 2)} / {f(e['p999'], 2)}; {e['n']} | "
+                     + (f"{f(g['max'], 2)} / {f(g['median'], 2)} |" if g else "- |"))
+    L.append("")
+    L.append("| process | oracle MEs/s (threads) | oracle MEs/s, 1 thread |")
+    L.append("|---|---|---|")
+    for row in rows:
+        o = row["oracle"]
+        L.append(f"| {row['process']} | {f(o['MEs_per_s'], 4)} ({o['threads']}) | {f(o['MEs_per_s_single_thread'], 4)} |")
+    return "\n".join(L) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -164,6 +276,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--sweep", action="store_true",
                     help="batch-size sweep 2^8..2^20 of every process instead of the benchmark line")
+    ap.add_argument("--table", default=None, metavar="MD_PATH",
+                    help="per-process table (FP64 and mixed MEs/s, roofline fractions, mixed errors, oracle "
+                         "MEs/s) as one JSON line, and as markdown to MD_PATH, instead of the benchmark line")
     ap.add_argument("--serving-processes", default="gg_tt,gg_ttg,gg_ttgg")
     ap.add_argument("--serving-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -188,6 +303,15 @@ def main():
         res = sweep(["ee_mumu", "gg_tt", "gg_ttg", "gg_ttgg", "gg_ttggg"], ["fp64", "mixed_fp16"], sizes, torch)
         print(json.dumps({"metric": "batch-size sweep: matrix elements/sec at 1 GPU", "unit": "MEs/s",
                           "data": "synthetic (RAMBO phase space on device, seed 0)", "sweep": res}), flush=True)
+        return
+    if args.table:
+        from tests import hostinfo
+        rows = process_table(torch)
+        with open(args.table, "w") as fh:
+            fh.write(table_markdown(rows))
+        print(json.dumps({"metric": "matrix elements/sec at 1 GPU per process: FP64 and mixed precision at stated "
+                                    "rel. err", "unit": "MEs/s", "cpu_model": hostinfo.cpu_model(),
+                          "data": "synthetic (RAMBO phase space, seed 0)", "table": rows}), flush=True)
         return
     log(f"bench: {name} n_evt={n_evt} steps={args.steps} warmup={args.warmup}")
 
@@ -255,7 +379,7 @@ def main():
         }),
     }
 
-    if info["n_partial_slots"] > 0 and n_evt > info["chunk_events"] // 2:
+    if info["n_partial_slots"] > 0 and n_evt > info["chunk_events"]:
         # chunks alternate between two streams, so two amplitude launches share the GPU and each
         # takes longer: the per-launch rate above is halved; the step-time rate is a lower bound
         # on the throughput of the amplitude work (the step also holds the colour sum)
@@ -288,7 +412,7 @@ def main():
                 # with the colour sum in the amplitude kernel: the helicity-sum kernel's time
                 "colour_sum_ms_per_step": ms_cs_m / args.steps,
             }
-            if pm.info["n_partial_slots"] > 0 and n_evt > pm.info["chunk_events"] // 2:
+            if pm.info["n_partial_slots"] > 0 and n_evt > pm.info["chunk_events"]:
                 # two streams: per-launch times overlap (as for FP64 above)
                 result[prec]["amplitude_kernel_tflops_per_step_time"] = flops_amp_step / (msm / 1e3) / 1e12
             log(f"{prec}: {msm:.3f} ms/step, {mesm:.4g} MEs/s, rel err max {rel.max():.2e} "
@@ -304,7 +428,8 @@ def main():
             result["serving"] = None
 
     if not args.no_cpu:
-        threads = min(16, len(os.sched_getaffinity(0)))
+        from tests import hostinfo
+        threads = hostinfo.host_threads()
         p, me_cpu, rate, dt = cpu_baseline(name, n_evt, W.PARAMS, args.cpu_seconds, threads)
         from tests import referee
         got = p64.sigma(torch.from_numpy(p).cuda()).cpu().numpy()
@@ -325,6 +450,7 @@ def main():
         oracle.me_batch(name, p[:n1], params=W.PARAMS, threads=1)
         rate1 = n1 / (time.perf_counter() - t1)
         result["cpu_baseline"] = {"value": rate, "unit": "MEs/s", "cores": threads, "kind": "oracle",
+                                  "cpu_model": hostinfo.cpu_model(),
                                   "sample": f"first {len(p)} events of the same RAMBO stream, {dt:.1f} s",
                                   "single_thread_value": rate1, "single_thread_sample": f"first {n1} events"}
         result["parity_sample"] = {"n": int(len(p)), "max_rel_err": float(rel.max()),

@@ -59,7 +59,11 @@ typedef struct me_handle me_handle; /* opaque, owned by the library */
 me_handle *me_create(const char *process, const double *masses, int n_masses,
                      const double *couplings, int n_couplings, int precision, void *stream);
 
-/* RAMBO phase-space points for the handle's process at energy sqrt_s:
+/* RAMBO phase-space points for the handle's process at energy sqrt_s.  In the paper's standalone
+ * application the random numbers and the phase-space sampling are simple components that can run
+ * entirely on the GPU beside the matrix element (Sec. 1); the generator (RAMBO) and the RNG are
+ * readings, as the paper names neither.  The handle argument (for the final-state masses) and
+ * evt0 (the first event of the stream, so that a batch can be made in pieces) are additions:
  * out = DEVICE double[n_evt][n_par][4], events evt0 .. evt0+n_evt-1 of the stream `seed`
  * (Philox4x64-10, key (seed, 0), counter (event * n_final + particle, 0, 0, 0)).  Beams are
  * particles 0 and 1 along +z and -z.  n_evt == 0 is a no-op.  ME_EINVAL for a NULL or host
@@ -67,7 +71,10 @@ me_handle *me_create(const char *process, const double *masses, int n_masses,
 int rambo_momenta(const me_handle *h, uint64_t seed, double sqrt_s, int64_t evt0, int64_t n_evt,
                   double *out, void *stream);
 
-/* out_me2[e] = averaged |M|^2 of event e for momenta = DEVICE double[n_evt][n_par][4]
+/* The matrix element of every event: the per-event, leading-order calculation the paper moves to
+ * the GPU with one lane of data parallelism per event (Sec. 1 and 2), here summed over helicities
+ * and colours and averaged over the initial states.
+ * out_me2[e] = averaged |M|^2 of event e for momenta = DEVICE double[n_evt][n_par][4]
  * (16-byte aligned).  n_evt == 0 is a no-op.  ME_EINVAL for NULL or host pointers,
  * misalignment or n_evt < 0.  Unphysical momenta are not checked (they give NaN/inf).
  * Work is split into chunks that bound the handle's per-stream scratch; calls on
@@ -164,6 +171,8 @@ typedef struct {
                                   amplitude kernel (every process but gg_ttggg) */
 } me_info_t;
 
+/* Reading (the paper defines no such call): sizes, counts and factors of a handle, for callers
+ * that size buffers, and for measurement (flop counts per lane). */
 int me_info(const me_handle *h, me_info_t *out);
 
 /* good helicities: out[k * n_par + i] = helicity (+1/-1) of particle i in the k-th good
@@ -200,9 +209,15 @@ int me_profile(me_handle *h, int enable, double *ms_amp, double *ms_colour, int6
 enum { ME_OPT_FUSED_COLOUR = 1 };
 int me_set_option(me_handle *h, int option, int value);
 
-const char *me_last_error(void); /* thread-local; valid until the thread's next call */
+/* Reading (the paper defines no error interface): the message of the calling thread's last
+ * failed call; thread-local, valid until the thread's next call. */
+const char *me_last_error(void);
 
-void me_destroy(me_handle *h); /* frees the handle and its device memory; NULL-safe */
+/* Frees the handle and its device memory (the colour tables, helicity list and per-stream
+ * scratch), after waiting for the device; NULL-safe.  Its place in the call sequence is the
+ * target's; that it waits for the device, not only for the streams the handle used, is a
+ * reading: those streams may be gone. */
+void me_destroy(me_handle *h);
 
 #ifdef __cplusplus
 }

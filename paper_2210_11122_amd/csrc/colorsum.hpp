@@ -134,10 +134,9 @@ __device__ __forceinline__ double cs64_column(const Load& load, const double* A,
 }
 
 // A operands, per lane, in the kernel's tile order (mt ascending, then kt >= 4 mt):
-// aop[q * 64 + l] = A[16 mt + l % 16][4 kt + l / 16].  JT: the jamps' storage type (float for the
-// mixed forms' small colour matrices, which a 16x16x32 tile would mostly pad with zeros).
-template <int NC, class JT = double>
-__global__ __launch_bounds__(256) void colour_sum_f64(const JT* __restrict__ J, int64_t ld, int n_good,
+// aop[q * 64 + l] = A[16 mt + l % 16][4 kt + l / 16].
+template <int NC>
+__global__ __launch_bounds__(256) void colour_sum_f64(const double* __restrict__ J, int64_t ld, int n_good,
                                                       int hel_per_group, int64_t n_evt,
                                                       const double* __restrict__ aop, double scale_hel,
                                                       double scale_avg, double* __restrict__ out,
@@ -160,7 +159,7 @@ __global__ __launch_bounds__(256) void colour_sum_f64(const JT* __restrict__ J, 
     }
     double me = 0.0;
     for (int h = h0; h < h1; ++h) {
-        const JT* Jh = J + (int64_t)h * (2 * NC) * ld;
+        const double* Jh = J + (int64_t)h * (2 * NC) * ld;
         const auto load = [&](int c, int ri) { return Jh[(int64_t)(2 * c + ri) * ld + ec]; };
         double part_h = sum_lane_groups(cs64_column<NC, AREG>(load, A, aop, lane));
         if (out_hel && g == 0 && valid) out_hel[e * n_good + h] = part_h * scale_hel;

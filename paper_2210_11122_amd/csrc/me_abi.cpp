@@ -178,10 +178,10 @@ struct ColourArgs {
     double *out, *out_hel, *part;
 };
 
-template <int NC, class JT = double>
-hipError_t launch_cs64(const JT* J, const double* aop, const ColourArgs& a, hipStream_t st)
+template <int NC>
+hipError_t launch_cs64(const double* J, const double* aop, const ColourArgs& a, hipStream_t st)
 {
-    hipLaunchKernelGGL((me::colour_sum_f64<NC, JT>), dim3((unsigned)((a.n + 63) / 64), (unsigned)a.groups), dim3(256),
+    hipLaunchKernelGGL((me::colour_sum_f64<NC>), dim3((unsigned)((a.n + 63) / 64), (unsigned)a.groups), dim3(256),
                        0, st, J, a.ld, a.n_good, a.hel_per_group, a.n, aop, a.scale_hel, a.scale_avg, a.out, a.out_hel,
                        a.part);
     return hipGetLastError();
@@ -199,7 +199,10 @@ template <class T>
 hipError_t dispatch_cs16(int nc, const float* j, const typename T::elem* aop, const typename T::elem* aop_lo,
                          uint64_t lo_mask, const ColourArgs& a, hipStream_t st)
 {
-    switch (nc) {  // N_c <= 6 goes to the FP64 matrix cores (colour_sum)
+    switch (nc) {
+    case 1: return launch_cs16<1, T>(j, aop, aop_lo, lo_mask, a, st);
+    case 2: return launch_cs16<2, T>(j, aop, aop_lo, lo_mask, a, st);
+    case 6: return launch_cs16<6, T>(j, aop, aop_lo, lo_mask, a, st);
     case 24: return launch_cs16<24, T>(j, aop, aop_lo, lo_mask, a, st);
     case 120: return launch_cs16<120, T>(j, aop, aop_lo, lo_mask, a, st);
     }
@@ -222,15 +225,6 @@ hipError_t colour_sum(const me_handle* h, int precision, const void* J, int64_t 
         case 6: e = launch_cs64<6>(j, h->d_aop64, a, st); break;
         case 24: e = launch_cs64<24>(j, h->d_aop64, a, st); break;
         case 120: e = launch_cs64<120>(j, h->d_aop64, a, st); break;
-        }
-    } else if (h->P->nc <= 6) {
-        // mixed forms, small colour matrices: the FP32 jamps on the FP64 matrix cores (a 16x16x32
-        // tile would be mostly padding; this is faster there and exact up to FP64 rounding)
-        const float* j = static_cast<const float*>(J);
-        switch (h->P->nc) {
-        case 1: e = launch_cs64<1, float>(j, h->d_aop64, a, st); break;
-        case 2: e = launch_cs64<2, float>(j, h->d_aop64, a, st); break;
-        case 6: e = launch_cs64<6, float>(j, h->d_aop64, a, st); break;
         }
     } else if (precision == ME_MIXED_FP16) {
         e = dispatch_cs16<me::Fp16Terms>(h->P->nc, static_cast<const float*>(J), h->d_aop16, h->d_aop16, 0, a, st);
@@ -355,10 +349,9 @@ int run_chunks(me_handle* h, int precision, const signed char* hel, int n_good, 
     // the colour sum inside the amplitude kernel: plain |M|^2 only (the selection, the
     // per-helicity output and the channel weights read the jamps)
     const bool fused = P->fused_colour && h->fuse_colour && !sel && !out_hel && !chan;
-    // the operand tables of the separate colour sum of this precision (small colour matrices:
-    // FP64 tiles in every precision)
+    // the operand tables of the separate colour sum of this precision
     me::FusedColour fcol{nullptr, nullptr, 0, precision};
-    if (precision == ME_FP64 || P->nc <= 6) fcol = {h->d_aop64, nullptr, 0, ME_FP64};
+    if (precision == ME_FP64) fcol = {h->d_aop64, nullptr, 0, ME_FP64};
     else if (precision == ME_MIXED_FP16) fcol.aop = h->d_aop16;
     else fcol = {h->d_aopb, h->d_aopb_lo, h->lo_mask_b16, precision};
     void* jamp = scratch;

@@ -509,11 +509,8 @@ class Process:
         if not fused:
             L.append("    if (fc) return hipErrorInvalidValue;  // no fused colour sum for this process")
         else:
-            if nc > 6:
-                L.append("    if (fc && (chan || !fc->aop || (sizeof(R) == 8) != (fc->form == ME_FP64))) "
-                         "return hipErrorInvalidValue;")
-            else:
-                L.append("    if (fc && (chan || !fc->aop || fc->form != ME_FP64)) return hipErrorInvalidValue;")
+            L.append("    if (fc && (chan || !fc->aop || (sizeof(R) == 8) != (fc->form == ME_FP64))) "
+                     "return hipErrorInvalidValue;")
             L.append("    const FusedColour none{nullptr, nullptr, 0, 0};")
         g64, g32 = WAVES_PER_GROUP.get(self.name, (1, 1))
         L.append(f"    constexpr int WG = sizeof(R) == 8 ? {g64} : {g32};  // waves (helicities) per workgroup")
@@ -671,18 +668,14 @@ class Process:
                     L.append("        for (int s = 0; s < 2 * NC; ++s) Js[s * 64 + lane] = Jr[s];")
                     L.append("        __syncthreads();")
                 L.append("        double me_h;")
-                if self.nc > 6:
-                    L.append("        if constexpr (sizeof(R) == 8)")
-                    L.append(f"            me_h = colour_sum_lds<NC>({src}, static_cast<const double*>(fc.aop), lane);")
-                    L.append("        else if (fc.form == ME_MIXED_BF16)")
-                    L.append(f"            me_h = colour_sum_lds_h16<NC, Bf16Terms>({src}, static_cast<const __bf16*>(fc.aop), "
-                             "static_cast<const __bf16*>(fc.aop_lo), fc.lo_mask, lane);")
-                    L.append("        else")
-                    L.append(f"            me_h = colour_sum_lds_h16<NC, Fp16Terms>({src}, static_cast<const _Float16*>(fc.aop), "
-                             "static_cast<const _Float16*>(fc.aop), 0, lane);")
-                else:
-                    # small colour matrices: FP64 tiles in every precision, as in the separate kernel
-                    L.append(f"        me_h = colour_sum_lds<NC>({src}, static_cast<const double*>(fc.aop), lane);")
+                L.append("        if constexpr (sizeof(R) == 8)")
+                L.append(f"            me_h = colour_sum_lds<NC>({src}, static_cast<const double*>(fc.aop), lane);")
+                L.append("        else if (fc.form == ME_MIXED_BF16)")
+                L.append(f"            me_h = colour_sum_lds_h16<NC, Bf16Terms>({src}, static_cast<const __bf16*>(fc.aop), "
+                         "static_cast<const __bf16*>(fc.aop_lo), fc.lo_mask, lane);")
+                L.append("        else")
+                L.append(f"            me_h = colour_sum_lds_h16<NC, Fp16Terms>({src}, static_cast<const _Float16*>(fc.aop), "
+                         "static_cast<const _Float16*>(fc.aop), 0, lane);")
                 L.append("        if (live && e < n_evt) reinterpret_cast<double*>(jamp)[(int64_t)h * n_evt + e] = me_h;")
                 L.append("        return;")
                 L.append("    }")

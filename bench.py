@@ -281,6 +281,8 @@ def main():
                          "MEs/s) as one JSON line, and as markdown to MD_PATH, instead of the benchmark line")
     ap.add_argument("--serving-processes", default="gg_tt,gg_ttg,gg_ttgg")
     ap.add_argument("--serving-seconds", type=float, default=10.0)
+    ap.add_argument("--serving-budget-mib", type=int, default=None,
+                    help="device-memory budget of the serving loop (default: 256 MiB without gg_ttggg, 32 GiB with it)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run one plain device copy of this size (for PMC byte calibration)")
     args = ap.parse_args()
@@ -422,8 +424,10 @@ def main():
     if not args.no_serving:
         try:
             from paper_2210_11122_amd import serve
+            budget = args.serving_budget_mib << 20 if args.serving_budget_mib else None
             result["serving"] = serve.bench_serving(duration_s=args.serving_seconds,
-                                                    processes=tuple(args.serving_processes.split(",")), log=log)
+                                                    processes=tuple(args.serving_processes.split(",")),
+                                                    hbm_budget=budget, log=log)
         except ImportError:
             result["serving"] = None
 

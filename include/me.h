@@ -104,6 +104,21 @@ int me_sigma(me_handle *h, const double *momenta, int64_t n_evt, double *out_me2
 #define ME_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
 int me_sigma_noalloc(me_handle *h, const double *momenta, int64_t n_evt, double *out_me2, void *stream);
 
+/* Scratch of a handle (a reading: the paper has no memory interface; a server that admits
+ * requests by device-memory footprint needs to know and bound what the library holds).  The
+ * scratch of calls on a stream is kept per (handle, stream), and per internal stream where a call
+ * uses them, and grows when a call needs more; it lives until me_release_scratch or me_destroy.
+ * The streams a handle was used on need not outlive it: me_destroy waits for the device.
+ * me_reserve_scratch: allocates now what every me_sigma / me_sigma_alphas call of at most n_evt
+ * events on `stream` needs, so that such calls allocate nothing more.  Synchronises `stream`
+ * only if an existing smaller buffer must be replaced.  ME_ENOMEM if the allocation fails.
+ * me_release_scratch: waits for `stream` (and its internal streams) and frees what the handle
+ * holds for calls on it.
+ * me_scratch_bytes: the bytes of scratch the handle holds now over all streams (< 0 on error). */
+int me_reserve_scratch(me_handle *h, int64_t n_evt, void *stream);
+int me_release_scratch(me_handle *h, void *stream);
+int64_t me_scratch_bytes(const me_handle *h);
+
 /* As me_sigma, and also out_hel[e * n_good + k] = colour-summed |M_h|^2 (not averaged) of
  * the k-th good helicity of event e (DEVICE double[n_evt][n_good], may be NULL). */
 int me_sigma_hel(me_handle *h, const double *momenta, int64_t n_evt, double *out_me2, double *out_hel,

@@ -36,7 +36,7 @@ class MeInfo(ctypes.Structure):
 
 
 EXPORTS = ["me_create", "me_destroy", "me_info", "me_last_error", "rambo_momenta", "me_sigma",
-           "me_sigma_noalloc", "me_sigma_hel", "me_sigma_select", "me_sigma_alphas", "me_sigma_channel", "me_diagrams", "me_colour_flows", "me_good_helicities", "me_helicity_ratios",
+           "me_sigma_noalloc", "me_reserve_scratch", "me_release_scratch", "me_scratch_bytes", "me_sigma_hel", "me_sigma_select", "me_sigma_alphas", "me_sigma_channel", "me_diagrams", "me_colour_flows", "me_good_helicities", "me_helicity_ratios",
            "me_profile", "me_set_option"]
 
 _lib = None
@@ -59,6 +59,10 @@ def load():
     L.rambo_momenta.argtypes = [vp, ctypes.c_uint64, ctypes.c_double, ctypes.c_int64, ctypes.c_int64, vp, vp]
     L.me_sigma.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
     L.me_sigma_noalloc.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
+    L.me_reserve_scratch.argtypes = [vp, ctypes.c_int64, vp]
+    L.me_release_scratch.argtypes = [vp, vp]
+    L.me_scratch_bytes.argtypes = [vp]
+    L.me_scratch_bytes.restype = ctypes.c_int64
     L.me_sigma_hel.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp]
     L.me_sigma_select.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp, vp, vp, vp]
     L.me_colour_flows.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
@@ -157,6 +161,19 @@ class Process:
         _check(load().me_sigma_noalloc(self._h, ctypes.c_void_p(momenta.data_ptr()), n,
                                        ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)), "me_sigma_noalloc")
         return out
+
+    def reserve_scratch(self, n_evt, stream=None):
+        """allocate now the scratch of every me_sigma call of at most n_evt events on `stream`"""
+        _check(load().me_reserve_scratch(self._h, int(n_evt), _stream_ptr(stream)), "me_reserve_scratch")
+
+    def release_scratch(self, stream=None):
+        _check(load().me_release_scratch(self._h, _stream_ptr(stream)), "me_release_scratch")
+
+    def scratch_bytes(self):
+        n = load().me_scratch_bytes(self._h)
+        if n < 0:
+            raise MeError(f"me_scratch_bytes failed: {last_error()}")
+        return n
 
     def select(self, momenta, r_hel, r_col, stream=None):
         """(|M|^2, helicity-combination index, colour-flow index) per event, the two choices

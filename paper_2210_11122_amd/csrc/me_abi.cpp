@@ -758,6 +758,28 @@ int sigma_piped(me_handle* h, const double* momenta, int64_t n_evt, double* out,
     return rc;
 }
 
+// How a call of n_evt events runs: equal chunks no larger than the handle's chunk; for processes
+// with segment kernels, the plain |M|^2 of more than one chunk alternates its chunks between two
+// internal streams, each with a scratch buffer of its own (full-size chunks keep the short segment
+// launches several rounds of waves deep).  Scratch per event of a chunk: the plain |M|^2 of a
+// kernel with the colour sum inside keeps one double per (event, helicity); otherwise the jamps
+// (and partial slots) of every helicity plus the helicity-group sums, and `extra` bytes.
+struct CallPlan {
+    int64_t chunk;
+    bool piped;
+    size_t per_event;
+};
+CallPlan plan_call(const me_handle* h, int64_t n_evt, bool plain, size_t extra)
+{
+    CallPlan c;
+    const int64_t n_chunks = (n_evt + h->chunk - 1) / h->chunk;
+    c.chunk = ((n_evt + n_chunks - 1) / n_chunks + 63) / 64 * 64;
+    c.piped = plain && h->P->nslot > 0 && n_evt > h->chunk;
+    const bool fused = plain && h->P->fused_colour && h->fuse_colour;
+    c.per_event = fused ? (size_t)h->n_good * sizeof(double) : h->bytes_per_event + extra;
+    return c;
+}
+
 // me_sigma and its variants: equal chunks through the stream's scratch
 int sigma_impl(me_handle* h, const double* momenta, int64_t n_evt, double* out_me2, double* out_hel,
                const Selection* sel_in, void* stream, const double* alphas = nullptr, const int* chan = nullptr)
@@ -775,22 +797,14 @@ int sigma_impl(me_handle* h, const double* momenta, int64_t n_evt, double* out_m
     if (chan && !h->P->sde_supported) return fail(ME_EINVAL, "no single-diagram channel weights for this process");
     if (reinterpret_cast<uintptr_t>(momenta) % 16 != 0) return fail(ME_EINVAL, "momenta must be 16-byte aligned");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    // processes with segment kernels, batches of more than one chunk: the chunks alternate
-    // between two internal streams, each with a scratch buffer of its own (twice the scratch;
-    // full-size chunks keep the short segment launches several rounds of waves deep); the plain
-    // |M|^2 only
-    const bool piped = h->P->nslot > 0 && !sel_in && !out_hel && !chan && n_evt > h->chunk;
-    const int64_t cap = h->chunk;
-    // equal chunks no larger than the scratch cap allows
-    const int64_t n_chunks = (n_evt + cap - 1) / cap;
-    const int64_t chunk = ((n_evt + n_chunks - 1) / n_chunks + 63) / 64 * 64;
-    if (piped) return sigma_piped(h, momenta, n_evt, out_me2, alphas, st, chunk);
     // selection adds |M_h|^2 and the leading-colour weights of one chunk
     const size_t sel_bytes = sel_in ? (size_t)(h->n_good + h->P->nc) * sizeof(double) : 0;
     // channel weights add two sums per (event, helicity)
     const size_t sde_bytes = chan ? (size_t)2 * h->n_good * sizeof(double) : 0;
-    const size_t need = (size_t)chunk * (h->bytes_per_event + sel_bytes + sde_bytes);
-    void* scratch = stream_scratch(h, st, need);
+    const CallPlan plan = plan_call(h, n_evt, !sel_in && !out_hel && !chan, sel_bytes + sde_bytes);
+    const int64_t chunk = plan.chunk;
+    if (plan.piped) return sigma_piped(h, momenta, n_evt, out_me2, alphas, st, chunk);
+    void* scratch = stream_scratch(h, st, (size_t)chunk * plan.per_event);
     if (!scratch) return fail(ME_ENOMEM, "hipMalloc of the jamp scratch failed");
     Selection sel{};
     if (sel_in) {
@@ -807,6 +821,62 @@ int sigma_impl(me_handle* h, const double* momenta, int64_t n_evt, double* out_m
 }
 
 }  // namespace
+
+int me_reserve_scratch(me_handle* h, int64_t n_evt, void* stream)
+{
+    if (!h) return fail(ME_EINVAL, "handle is NULL");
+    if (n_evt < 0) return fail(ME_EINVAL, "negative event count");
+    if (n_evt == 0) return ME_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // every plain call of at most n_evt events: chunks of at most min(n_evt rounded up, chunk) on
+    // `stream`, and full chunks on both internal streams where such a call is piped
+    const CallPlan one = plan_call(h, std::min<int64_t>(n_evt, h->chunk), true, 0);
+    if (!stream_scratch(h, st, (size_t)one.chunk * one.per_event))
+        return fail(ME_ENOMEM, "hipMalloc of the jamp scratch failed");
+    if (plan_call(h, n_evt, true, 0).piped) {
+        Helpers* hp = helpers_for(st);
+        if (!hp) return fail(ME_EHIP, "creating the internal streams failed");
+        for (int i = 0; i < 2; ++i)
+            if (!stream_scratch(h, hp->s[i], (size_t)h->chunk * h->bytes_per_event))
+                return fail(ME_ENOMEM, "hipMalloc of the jamp scratch failed");
+    }
+    return ME_OK;
+}
+
+int me_release_scratch(me_handle* h, void* stream)
+{
+    if (!h) return fail(ME_EINVAL, "handle is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    std::vector<hipStream_t> ss{st};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(ME_EHIP, "hipGetDevice failed");
+    {
+        std::lock_guard<std::mutex> lk(g_helpers_mu);
+        auto it = g_helpers.find({dev, st});
+        if (it != g_helpers.end())
+            for (int i = 0; i < 2; ++i)
+                if (it->second.s[i]) ss.push_back(it->second.s[i]);
+    }
+    std::lock_guard<std::mutex> lk(h->mu);
+    int rc = ME_OK;
+    for (hipStream_t x : ss) {
+        auto it = h->scratch.find(x);
+        if (it == h->scratch.end()) continue;
+        if (it->second.ptr && (hipStreamSynchronize(x) != hipSuccess || hipFree(it->second.ptr) != hipSuccess))
+            rc = fail(ME_EHIP, "freeing the jamp scratch failed");
+        h->scratch.erase(it);
+    }
+    return rc;
+}
+
+int64_t me_scratch_bytes(const me_handle* h)
+{
+    if (!h) return fail(ME_EINVAL, "handle is NULL");
+    std::lock_guard<std::mutex> lk(const_cast<me_handle*>(h)->mu);
+    int64_t n = 0;
+    for (auto& kv : h->scratch) n += (int64_t)kv.second.bytes;
+    return n;
+}
 
 int me_sigma_hel(me_handle* h, const double* momenta, int64_t n_evt, double* out_me2, double* out_hel, void* stream)
 {

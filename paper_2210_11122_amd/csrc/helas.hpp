@@ -472,6 +472,15 @@ __device__ __forceinline__ void pin_p4(P4& p)
 {
     if constexpr (sizeof(R) == 8) asm volatile("" : "+v"(p.t), "+v"(p.x), "+v"(p.y), "+v"(p.z));
 }
+// Makes an amplitude's value opaque once computed: the operations that produce it cannot be
+// fused with those that consume it, so every instance of a kernel (with or without the
+// channel-weight sums, whose extra uses of the value change what the compiler may contract)
+// rounds it the same way.
+template <class R>
+__device__ __forceinline__ void pin_cx(cx<R>& a)
+{
+    asm volatile("" : "+v"(a.r), "+v"(a.i));
+}
 // LDS atomic add into this lane's private jamp slot (no return value: ds_add_f64 / ds_add_f32)
 template <class R>
 __device__ __forceinline__ void lds_add(R* p, R v)

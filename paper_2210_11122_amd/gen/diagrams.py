@@ -21,6 +21,7 @@ The amplitude vertex of a diagram is either a quark-gluon vertex on the line (FF
 root vertex of one of its trees (VVV / VVVV with the JF current as one leg); it is chosen
 per diagram, greedily, to minimise the total cost of the distinct currents.
 """
+from fractions import Fraction
 from functools import lru_cache
 from itertools import combinations
 
@@ -286,12 +287,14 @@ def node_size(key, remat_ext=False):
     return 16
 
 
-def schedule(plan, remat_ext=False):
+def schedule(plan, remat_ext=False, amps=None):
     """Order the amplitudes (and the nodes they need, computed just before their first
     use) greedily so that few computed currents are live at once: at each step take the
     amplitude that needs the fewest new registers net of the registers it frees.
-    Returns [(diagram index, option, deps)] in evaluation order."""
-    amps = plan.amplitudes()
+    amps: the units to order (default: the plan's amplitudes), each (diagram index, option,
+    deps); a unit may stand for several amplitudes evaluated in a row (deps: all of theirs).
+    Returns the units in evaluation order."""
+    amps = plan.amplitudes() if amps is None else amps
     nodes = plan.nodes()
     consumers = {k: 0 for k in nodes}
     for k in nodes:
@@ -427,6 +430,43 @@ def schedule_window(amps, nodes, jamp_sets, beta, window):
     return order
 
 
+def proportional_classes(jcoef, perm_index):
+    """Amplitude entries whose colour coefficients are proportional: [[(entry, (ur, ui)), ..]],
+    where entry m's coefficients are (ur + i ui) times the first member's on every colour flow
+    (a unit of the Gaussian integers).  Such entries add to the same jamps in the same ratio, so
+    their amplitudes can be summed first (J_k += c_k (a_1 + u_2 a_2 + ..)): one set of jamp
+    updates per class instead of one per entry.  Classes are listed by their first entry."""
+    groups = {}
+    for di, coef in enumerate(jcoef):
+        co = {perm_index[q]: c for q, c in coef.items()}
+        k0 = min(co)
+        c0 = co[k0]
+        n0 = c0.re * c0.re + c0.im * c0.im
+        key, unit = [], None
+        for k in sorted(co):
+            # co[k] / c0 as an exact pair of fractions
+            c = co[k]
+            r = (Fraction(c.re * c0.re + c.im * c0.im, n0), Fraction(c.im * c0.re - c.re * c0.im, n0))
+            key.append((k, r))
+        key = tuple(key)
+        groups.setdefault(key, []).append((di, co))
+    out = []
+    for members in sorted(groups.values(), key=lambda m: m[0][0]):
+        d0, co0 = members[0]
+        k0 = min(co0)
+        row = []
+        for di, co in members:
+            a, b = co[k0], co0[k0]   # unit u with co = u * co0
+            nb = b.re * b.re + b.im * b.im
+            ur = (a.re * b.re + a.im * b.im) // nb
+            ui = (a.im * b.re - a.re * b.im) // nb
+            assert ur * b.re - ui * b.im == a.re and ur * b.im + ui * b.re == a.im
+            assert (ur, ui) in ((1, 0), (-1, 0), (0, 1), (0, -1))
+            row.append((di, (ur, ui)))
+        out.append(row)
+    return out
+
+
 def closure(deps):
     need, st = set(), list(deps)
     while st:
@@ -438,10 +478,11 @@ def closure(deps):
     return need
 
 
-def segment_plan(plan, jamp_sets, n_segments, beta, window):
+def segment_plan(plan, jamp_sets, n_segments, beta, window, amps=None):
     """Cut the jamp-aware order into n_segments contiguous pieces (one kernel each, which
-    recomputes the currents it needs) and reorder each piece the same way."""
-    amps = plan.amplitudes()
+    recomputes the currents it needs) and reorder each piece the same way.  amps: the units
+    to order (default: the plan's amplitudes; see `schedule`)."""
+    amps = plan.amplitudes() if amps is None else amps
     order = schedule_window(amps, plan.nodes(), jamp_sets, beta, window)
     n = len(order)
     segs = []

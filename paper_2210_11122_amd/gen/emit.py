@@ -30,6 +30,11 @@ FLOPS = {
 QCD_PROCESSES = {"gg_tt": 2, "gg_ttg": 3, "gg_ttgg": 4, "gg_ttggg": 5}
 # name -> (segment kernels, LDS jamp-window slots, weight of window misses in the schedule)
 SEGMENTS = {"gg_ttggg": (14, 28, 1.0)}
+# sum the amplitudes of entries with proportional colour coefficients before their jamp updates
+PRESUM = True
+# sa += u a for the units u of the Gaussian integers
+ACC_TEXT = {(1, 0): "sa.r += a.r; sa.i += a.i;", (-1, 0): "sa.r -= a.r; sa.i -= a.i;",
+            (0, 1): "sa.r -= a.i; sa.i += a.r;", (0, -1): "sa.r += a.i; sa.i -= a.r;"}
 # read each amplitude step's momenta from LDS ahead of the previous step's jamp updates
 PREFETCH_MOMENTA = True
 # and keep the compiler from summing them before the step that uses them
@@ -101,6 +106,11 @@ class Process:
         self.n_diagrams = sum(1 for d in self.diagrams if D.is_canonical_structure(d))
         self.n_amplitudes = len(self.diagrams)
         self.jcoef = [D.diagram_colour(d, dkind) for d in self.diagrams]
+        self.perm_index = {tuple(p): i for i, p in enumerate(self.perms)}
+        if PRESUM:
+            self.classes = D.proportional_classes(self.jcoef, self.perm_index)
+        else:
+            self.classes = [[(di, (1, 0))] for di in range(len(self.diagrams))]
         self.plan = D.Plan(self.diagrams, dkind)
         self._single_diagram_data(C)
 
@@ -283,54 +293,74 @@ class Process:
             return nm
 
         if order is None:
-            order = D.schedule(self.plan, remat_ext=remat_ext)
-        for ai, (di, opt, deps) in enumerate(order):
-            d = self.diagrams[di]
-            kind, j = opt
-            m_node = len(out)
-            if kind == "FFV":
-                wu, wv, wg = (emit(k) for k in deps)
-                m_amp = len(out)
-                out.append(f"    a = amp_ffv<R>({wu}, {wv}, {wg}, gs);")
-                flops[0] += FLOPS["amp_ffv"]
-            else:
-                t = d[j]
-                kids = D.children(t)
-                wx = emit(deps[0])
-                ws = [emit(k) for k in deps[1:]]
-                m_amp = len(out)
-                if self.kind == "gluon":
-                    kx = K((self.ng - 1,))
+            order = D.schedule(self.plan, remat_ext=remat_ext, amps=self.units())
+        # the amplitude entries in the order their `a = amp_...` lines are emitted
+        self.emit_order = [m[0] for unit in order for m in self.unit_members(unit)]
+        for ai, unit in enumerate(order):
+            members = self.unit_members(unit)
+            for mi, (di, opt, deps, (ur, ui)) in enumerate(members):
+                last = mi == len(members) - 1
+                d = self.diagrams[di]
+                kind, j = opt
+                m_node = len(out)
+                if kind == "FFV":
+                    wu, wv, wg = (emit(k) for k in deps)
+                    m_amp = len(out)
+                    out.append(f"    a = amp_ffv<R>({wu}, {wv}, {wg}, gs);")
+                    flops[0] += FLOPS["amp_ffv"]
                 else:
-                    kx = "(-" + K(D.leaves(t)) + ")"
-                if t[0] == "V3":
-                    ka, kb = K(D.leaves(kids[0])), K(D.leaves(kids[1]))
-                    out.append(f"    a = amp_vvv<R>({wx}, {kx}, {ws[0]}, {ka}, {ws[1]}, {kb}, gs);")
-                    flops[0] += FLOPS["amp_vvv"]
+                    t = d[j]
+                    kids = D.children(t)
+                    wx = emit(deps[0])
+                    ws = [emit(k) for k in deps[1:]]
+                    m_amp = len(out)
+                    if self.kind == "gluon":
+                        kx = K((self.ng - 1,))
+                    else:
+                        kx = "(-" + K(D.leaves(t)) + ")"
+                    if t[0] == "V3":
+                        ka, kb = K(D.leaves(kids[0])), K(D.leaves(kids[1]))
+                        out.append(f"    a = amp_vvv<R>({wx}, {kx}, {ws[0]}, {ka}, {ws[1]}, {kb}, gs);")
+                        flops[0] += FLOPS["amp_vvv"]
+                    else:
+                        out.append(f"    a = amp_vvvv<R, {t[1]}>({wx}, {ws[0]}, {ws[1]}, {ws[2]}, gs);")
+                        flops[0] += FLOPS["amp_vvvv"]
+                out.append("    pin_cx<R>(a);")
+                if self.fd_index is not None:
+                    out.append(f"    SDEACC({self.fd_index[di]}, {self.kweight[di]!r});")
+                # amplitudes of a class with proportional colour coefficients are summed first:
+                # sa = a_1, then sa += u_m a_m; its jamp updates use sa
+                if len(members) > 1:
+                    if mi == 0:
+                        out.append("    sa = a;")
+                    else:
+                        out.append("    " + ACC_TEXT[(ur, ui)])
+                        flops[0] += FLOPS["jamp"]
+                marks.append((m_node, m_amp, len(out)))
+                if not last:
+                    if prefetch and steps is not None:
+                        puts.append([])
+                    continue
+                var = "sa" if len(members) > 1 else "a"
+                di0 = members[0][0]
+                if steps is None:
+                    for seq, c in sorted(self.jcoef[di0].items()):
+                        out.append(self._jamp_update(self.perm_index[seq], c, var))
+                        flops[0] += FLOPS["jamp"]
                 else:
-                    out.append(f"    a = amp_vvvv<R, {t[1]}>({wx}, {ws[0]}, {ws[1]}, {ws[2]}, gs);")
-                    flops[0] += FLOPS["amp_vvvv"]
-            if self.fd_index is not None:
-                out.append(f"    SDEACC({self.fd_index[di]}, {self.kweight[di]!r});")
-            marks.append((m_node, m_amp, len(out)))
-            if steps is None:
-                for seq, c in sorted(self.jcoef[di].items()):
-                    out.append(self._jamp_update(self.perm_index[seq], c))
-                    flops[0] += FLOPS["jamp"]
-            else:
-                coef = {self.perm_index[seq]: c for seq, c in self.jcoef[di].items()}
-                mine = []
-                for j, slot, flush in steps[ai]:
-                    if flush is not None:
-                        k = flush[1]
-                        out.append(f"    JTAKE({flush[0]}, {k});")
-                        mine.append(f"    JPUT({k}, {k});")
-                    out.append(self._jamp_update(slot, coef[j]))
-                    flops[0] += FLOPS["jamp"]
-                if prefetch:
-                    puts.append(mine)
-                else:
-                    out += mine
+                    coef = {self.perm_index[seq]: c for seq, c in self.jcoef[di0].items()}
+                    mine = []
+                    for j, slot, flush in steps[ai]:
+                        if flush is not None:
+                            k = flush[1]
+                            out.append(f"    JTAKE({flush[0]}, {k});")
+                            mine.append(f"    JPUT({k}, {k});")
+                        out.append(self._jamp_update(slot, coef[j], var))
+                        flops[0] += FLOPS["jamp"]
+                    if prefetch:
+                        puts.append(mine)
+                    else:
+                        out += mine
         tail = []
         if puts:
             tail += puts[-1]
@@ -344,19 +374,45 @@ class Process:
         return flops[0]
 
     @staticmethod
-    def _jamp_update(s, c):
-        """J[s] += c * a through the JADD(slot, re/im, value) macro"""
+    def _jamp_update(s, c, v="a"):
+        """J[s] += c * v (v: the amplitude a, or a class sum s) through the JADD(slot, re/im,
+        value) macro"""
         cr, ci = c.re, c.im
         if (cr, ci) == (1, 0):
-            return f"    JADD({s}, 0, a.r); JADD({s}, 1, a.i);"
+            return f"    JADD({s}, 0, {v}.r); JADD({s}, 1, {v}.i);"
         if (cr, ci) == (-1, 0):
-            return f"    JADD({s}, 0, -a.r); JADD({s}, 1, -a.i);"
+            return f"    JADD({s}, 0, -{v}.r); JADD({s}, 1, -{v}.i);"
         if (cr, ci) == (0, 1):
-            return f"    JADD({s}, 0, -a.i); JADD({s}, 1, a.r);"
+            return f"    JADD({s}, 0, -{v}.i); JADD({s}, 1, {v}.r);"
         if (cr, ci) == (0, -1):
-            return f"    JADD({s}, 0, a.i); JADD({s}, 1, -a.r);"
-        return (f"    JADD({s}, 0, (R)({cr}) * a.r - (R)({ci}) * a.i); "
-                f"JADD({s}, 1, (R)({cr}) * a.i + (R)({ci}) * a.r);")
+            return f"    JADD({s}, 0, {v}.i); JADD({s}, 1, -{v}.r);"
+        return (f"    JADD({s}, 0, (R)({cr}) * {v}.r - (R)({ci}) * {v}.i); "
+                f"JADD({s}, 1, (R)({cr}) * {v}.i + (R)({ci}) * {v}.r);")
+
+    # -----------------------------------------------------------------------------------
+    # units of the diagram program: classes of amplitude entries with proportional colour
+    # coefficients (singletons when PRESUM is off)
+
+    def units(self):
+        """[(first entry, ("CLASS", members), deps of all members)], members = ((entry, option,
+        deps, unit factor), ..); the order of self.classes"""
+        if getattr(self, "_units", None) is None:
+            amps = {a[0]: a for a in self.plan.amplitudes()}
+            out = []
+            for cls in self.classes:
+                mem = tuple((di, amps[di][1], amps[di][2], u) for di, u in cls)
+                deps = tuple(dict.fromkeys(k for m in mem for k in m[2]))
+                out.append((cls[0][0], ("CLASS", mem), deps))
+            self._units = out
+        return self._units
+
+    @staticmethod
+    def unit_members(unit):
+        """the (entry, option, deps, unit factor) of each amplitude a unit stands for"""
+        di, opt, deps = unit
+        if opt[0] == "CLASS":
+            return opt[1]
+        return ((di, opt, deps, (1, 0)),)
 
     def _emit_ee_body(self, out):
         # (e+, e-, mu+, mu-): vbar(p0) (i e gamma) u(p1) -> photon -> ubar(p3) (i e gamma) v(p2)
@@ -414,8 +470,9 @@ class Process:
             n_seg, window, beta = self.segments
             jsets = [set(self.perm_index[q] for q in self.jcoef[i]) for i in range(len(self.diagrams))]
             # algorithmic count: every node once, in any order
-            fl = self._emit_qcd_body([], remat_ext, order=self.plan.amplitudes())
-            segs = D.segment_plan(self.plan, jsets, n_seg, beta, window)
+            fl = self._emit_qcd_body([], remat_ext, order=self.units())
+            segs = D.segment_plan(self.plan, jsets, n_seg, beta, window, amps=self.units())
+            self.segment_orders = segs
             self.flops_exec = 0
             partial_jamp = []
             for k, order in enumerate(segs):
@@ -634,7 +691,7 @@ class Process:
             L.append("#define JLAST(s, k) const R fr##k = JGET(s, 0), fi##k = JGET(s, 1)")
             L.append("#define JPUT(p, k) do { if (live) { po[(int64_t)(2 * (p)) * ld] = fr##k; "
                      "po[(int64_t)(2 * (p) + 1) * ld] = fi##k; } } while (0)")
-        L.append("    cx<R> a;")
+        L.append("    cx<R> a, sa;")
         L.append("    int ch = -1;")
         L.append("    double sde_ch = 0.0, sde_all = 0.0;")
         L.append("    if constexpr (SDE) ch = (e < n_evt) ? chan[e] : -1;")

@@ -155,7 +155,7 @@ def test_window_program_reproduces_direct_accumulation():
     perm_index = {tuple(p): i for i, p in enumerate(P.perms)}
     jsets = [set(perm_index[q] for q in P.jcoef[i]) for i in range(len(P.diagrams))]
     n_seg, window, beta = P.segments
-    segs = D.segment_plan(P.plan, jsets, n_seg, beta, window)
+    segs = P.segment_orders
     rng = np.random.default_rng(0)
     amp = rng.normal(size=len(P.diagrams)) + 1j * rng.normal(size=len(P.diagrams))
     direct = np.zeros(P.nc, complex)
@@ -168,15 +168,22 @@ def test_window_program_reproduces_direct_accumulation():
     for order in segs:
         steps, final, pj = D.window_program(order, jsets, window)
         win = np.zeros(window, complex)
-        for (di, _, _), ops in zip(order, steps):
-            seen.append(di)
+        for unit, ops in zip(order, steps):
+            # a unit: entries with proportional colour coefficients, summed with their factors
+            members = P.unit_members(unit)
+            seen += [m[0] for m in members]
+            a = sum(complex(*m[3]) * amp[m[0]] for m in members)
+            di = members[0][0]
             coef = {perm_index[q]: c for q, c in P.jcoef[di].items()}
+            for m in members:
+                cm = {perm_index[q]: complex(c.re, c.im) for q, c in P.jcoef[m[0]].items()}
+                assert all(abs(cm[k] - complex(*m[3]) * complex(coef[k].re, coef[k].im)) == 0 for k in coef)
             for j, slot, flush in ops:
                 if flush is not None:
                     partial[base + flush[1]] = win[flush[0]]
                     win[flush[0]] = 0
                 c = coef[j]
-                win[slot] += complex(c.re, c.im) * amp[di]
+                win[slot] += complex(c.re, c.im) * a
         for slot, pidx, _ in final:
             partial[base + pidx] = win[slot]
         base += len(pj)
@@ -199,7 +206,7 @@ def test_emitted_window_kernels_and_reduction_accumulate_every_jamp():
     perm_index = {tuple(p): i for i, p in enumerate(P.perms)}
     jsets = [set(perm_index[q] for q in P.jcoef[i]) for i in range(len(P.diagrams))]
     n_seg, window, beta = P.segments
-    segs = D.segment_plan(P.plan, jsets, n_seg, beta, window)
+    segs = P.segment_orders
     rng = np.random.default_rng(1)
     amp = rng.normal(size=len(P.diagrams)) + 1j * rng.normal(size=len(P.diagrams))
     direct = np.zeros(P.nc, complex)
@@ -215,14 +222,25 @@ def test_emitted_window_kernels_and_reduction_accumulate_every_jamp():
         body = text[text.index("#define SDEACC"):text.index("\n    if constexpr (SDE) {\n")]
         win = np.zeros(window, complex)
         fr = {}
-        it = iter(order)
-        a = None
+        it = iter([m[0] for unit in order for m in P.unit_members(unit)])
+        a = sa = None
+        acc = {"sa.r += a.r; sa.i += a.i;": 1, "sa.r -= a.r; sa.i -= a.i;": -1,
+               "sa.r -= a.i; sa.i += a.r;": 1j, "sa.r += a.i; sa.i -= a.r;": -1j}
         for line in body.splitlines()[1:]:
             if re.match(r"\s*a = amp", line):
-                a = amp[next(it)[0]]
+                a = amp[next(it)]
+                continue
+            if line.strip() == "sa = a;":
+                sa = a
+                continue
+            if line.strip() in acc:
+                sa = sa + acc[line.strip()] * a
                 continue
             for s_, ri, v in jadd.findall(line):
-                val = eval(v.replace("(R)", "").replace("a.r", "ar").replace("a.i", "ai"), {"ar": a.real, "ai": a.imag})
+                env = {"ar": a.real, "ai": a.imag, "sar": sa.real if sa is not None else 0,
+                       "sai": sa.imag if sa is not None else 0}
+                val = eval(v.replace("(R)", "").replace("sa.r", "sar").replace("sa.i", "sai")
+                           .replace("a.r", "ar").replace("a.i", "ai"), env)
                 win[int(s_)] += val if ri == "0" else 1j * val
             for m, x, y in macro.findall(line):
                 x, y = int(x), int(y)
@@ -239,6 +257,48 @@ def test_emitted_window_kernels_and_reduction_accumulate_every_jamp():
     lst = [int(v) for v in re.search(r"slot_list\[NSLOT\] = \{([^}]*)\}", src).group(1).split(",")]
     red = np.array([sum(partial[lst[i]] for i in range(offs[c], offs[c + 1])) for c in range(P.nc)])
     assert np.allclose(red, direct, rtol=0, atol=1e-12 * np.abs(direct).max())
+
+
+@pytest.mark.parametrize("name", ["gg_ttg", "gg_ttgg", "gg_gg"])
+def test_emitted_kernel_accumulates_every_jamp(name):
+    """interpret the emitted single-kernel program (amplitudes, class sums sa, JADD updates) with
+    random amplitudes: every jamp equals direct accumulation of every entry's colour coefficients"""
+    P = emit.Process(name)
+    src = P.source()
+    perm_index = {tuple(p): i for i, p in enumerate(P.perms)}
+    rng = np.random.default_rng(2)
+    amp = rng.normal(size=len(P.diagrams)) + 1j * rng.normal(size=len(P.diagrams))
+    direct = np.zeros(P.nc, complex)
+    for di in range(len(P.diagrams)):
+        for q, c in P.jcoef[di].items():
+            direct[perm_index[q]] += complex(c.re, c.im) * amp[di]
+    body = src[src.index("#define SDEACC"):src.index("\n    if constexpr (SDE) {\n")]
+    jadd = re.compile(r"JADD\((\d+), ([01]), ([^;]*)\);")
+    acc = {"sa.r += a.r; sa.i += a.i;": 1, "sa.r -= a.r; sa.i -= a.i;": -1,
+           "sa.r -= a.i; sa.i += a.r;": 1j, "sa.r += a.i; sa.i -= a.r;": -1j}
+    assert sorted(P.emit_order) == list(range(len(P.diagrams)))
+    it = iter(P.emit_order)
+    J = np.zeros(P.nc, complex)
+    a = sa = None
+    for line in body.splitlines()[1:]:
+        t = line.strip()
+        if re.match(r"a = amp", t):
+            a = amp[next(it)]
+        elif t == "sa = a;":
+            sa = a
+        elif t in acc:
+            sa = sa + acc[t] * a
+        for s_, ri, v in jadd.findall(line):
+            env = {"ar": a.real, "ai": a.imag, "sar": sa.real if sa is not None else 0,
+                   "sai": sa.imag if sa is not None else 0}
+            val = eval(v.replace("(R)", "").replace("sa.r", "sar").replace("sa.i", "sai")
+                       .replace("a.r", "ar").replace("a.i", "ai"), env)
+            J[int(s_)] += val if ri == "0" else 1j * val
+    assert next(it, None) is None
+    assert np.allclose(J, direct, rtol=0, atol=1e-12 * np.abs(direct).max())
+    if name == "gg_ttgg":
+        # entries with proportional coefficients share one set of updates: 336 instead of 672
+        assert len(jadd.findall(body)) == 2 * 336
 
 
 @pytest.mark.parametrize("name", ["gg_tt", "gg_ttg", "gg_ttgg"])

@@ -191,7 +191,51 @@ __device__ __forceinline__ W4<R> ext_vbar(const P4& p, double m, int lam)
     w.c[3] = {v.c[1].r, -v.c[1].i};
     return w;
 }
-// gluon / photon polarisation vector of momentum k; complex conjugate if outgoing
+// The polarisation vectors of a massless vector boson are fixed by five numbers of its
+// direction (theta, phi), r = 1/sqrt(2):
+//   a = r cos(theta) cos(phi), b = r cos(theta) sin(phi), c = r sin(theta),
+//   d = r sin(phi), e = r cos(phi)
+// (along +-z: phi = 0).  The helicity and the conjugation of an outgoing boson only flip signs.
+template <class T>
+struct GBT {
+    T a, b, c, d, e;
+};
+typedef GBT<double> GB;
+__device__ __forceinline__ GB gluon_basis(const P4& k)
+{
+    double kt2 = k.x * k.x + k.y * k.y;
+    double ikk = rsqrt_nr(kt2 + k.z * k.z);
+    double ct = k.z * ikk, st = 0.0, cp = 1.0, sp = 0.0;
+    if (kt2 > 0.0) {
+        double ikt = rsqrt_nr(kt2);
+        st = kt2 * ikt * ikk;
+        cp = k.x * ikt;
+        sp = k.y * ikt;
+    }
+    const double r = 0.70710678118654752440;
+    return {r * ct * cp, r * ct * sp, r * st, r * sp, r * cp};
+}
+// the basis in the working precision (rounding commutes with the sign flips below, so the
+// vectors are those of the FP64 basis rounded)
+template <class R>
+__device__ __forceinline__ GBT<R> gb_cast(const GB& g)
+{
+    return {(R)g.a, (R)g.b, (R)g.c, (R)g.d, (R)g.e};
+}
+// polarisation vector of helicity lam from the basis; complex conjugate if outgoing
+template <class R>
+__device__ __forceinline__ W4<R> ext_vec_b(const GBT<R>& g, int lam, bool outgoing)
+{
+    const R m = (R)(-lam);   // exact: lam = +-1
+    W4<R> w;
+    w.c[0] = {(R)0, (R)0};
+    w.c[1] = {m * g.a, outgoing ? -g.d : g.d};
+    w.c[2] = {m * g.b, outgoing ? g.e : -g.e};
+    w.c[3] = {-m * g.c, (R)0};
+    return w;
+}
+// gluon / photon polarisation vector of momentum k; complex conjugate if outgoing (the same
+// values as ext_vec_b of gluon_basis(k): the products below differ from those only by signs)
 template <class R>
 __device__ __forceinline__ W4<R> ext_vec(const P4& k, int lam, bool outgoing)
 {
@@ -450,6 +494,25 @@ __device__ __forceinline__ void stage_momenta(const double* __restrict__ mom, in
     __syncthreads();
 }
 
+// as stage_momenta, for a workgroup of `threads` threads known only at run time
+template <int NPAR>
+__device__ __forceinline__ void stage_momenta_n(const double* __restrict__ mom, int64_t n_evt, int64_t e0,
+                                                double* lds, int tid, int threads)
+{
+    constexpr int NCOMP = 4 * NPAR;
+    constexpr int NLOAD = 64 * NCOMP / 2;  // double2 elements of the block
+    const double2* src = reinterpret_cast<const double2*>(mom + e0 * NCOMP);
+    const int64_t n_here = (n_evt - e0) < 64 ? (n_evt - e0) : 64;
+    for (int f = tid; f < NLOAD; f += threads) {
+        const int ev = (2 * f) / NCOMP;
+        const int c = (2 * f) % NCOMP;
+        double2 v = {0.0, 0.0};
+        if (ev < n_here) v = src[f];
+        reinterpret_cast<double2*>(lds)[(c / 2) * 64 + ev] = v;
+    }
+    __syncthreads();
+}
+
 }  // namespace me
 
 namespace me {
@@ -462,6 +525,41 @@ __device__ __forceinline__ P4 lds_p4(const double* lds, int i, int lane)
     lds_v2d* v = (lds_v2d*)lds;
     const v2d a = v[(2 * i) * 64 + lane], b = v[(2 * i + 1) * 64 + lane];
     return {a.x, a.y, b.x, b.y};
+}
+// Gluon bases of the block's events in LDS (shared by every helicity wave of the workgroup),
+// in the working precision R, written once after the momenta are staged: for gluon j (particle
+// gp[j]) and event ev, three pairs (a, b), (c, d), (e, 0) at gbl[(3 j + q) * 64 + ev].  Programs
+// that keep no external gluon wavefunction in registers rebuild it from here at each use.
+template <class R, int NGL, int WG>
+__device__ __forceinline__ void stage_gluon_basis(const double* lds, R* gbl, const int (&gp)[NGL], int tid)
+{
+    typedef R v2 __attribute__((ext_vector_type(2)));
+    v2* g2 = reinterpret_cast<v2*>(gbl);
+    const int wave = tid >> 6, ev = tid & 63;
+#pragma unroll
+    for (int j = 0; j < NGL; ++j) {  // gluon j by wave j % WG, one event per lane
+        if (j % WG != wave) continue;
+        const GBT<R> g = gb_cast<R>(gluon_basis(lds_p4(lds, gp[j], ev)));
+        g2[(3 * j) * 64 + ev] = {g.a, g.b};
+        g2[(3 * j + 1) * 64 + ev] = {g.c, g.d};
+        g2[(3 * j + 2) * 64 + ev] = {g.e, (R)0};
+    }
+    __syncthreads();
+}
+// gluon j's basis for this lane's event, re-read from LDS at every use (volatile, as lds_p4)
+template <class R>
+__device__ __forceinline__ GBT<R> lds_gb(const R* gbl, int j, int lane)
+{
+    typedef R v2 __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(3))) const volatile v2 lds_v2;
+    lds_v2* v = (lds_v2*)gbl;
+    const v2 x = v[(3 * j) * 64 + lane], y = v[(3 * j + 1) * 64 + lane], z = v[(3 * j + 2) * 64 + lane];
+    return {x.x, x.y, y.x, y.y, z.x};
+}
+template <class R>
+__device__ __forceinline__ void pin_gb(GBT<R>& g)
+{
+    if constexpr (sizeof(R) == 8) asm volatile("" : "+v"(g.a), "+v"(g.b), "+v"(g.c), "+v"(g.d), "+v"(g.e));
 }
 // Marks a four-momentum as first needed here: arithmetic on it (momentum sums) cannot be
 // moved above this point, so a value read from LDS early need not be waited for earlier.

@@ -350,10 +350,12 @@ int run_chunks(me_handle* h, int precision, const signed char* hel, int n_good, 
     // per-helicity output and the channel weights read the jamps)
     const bool fused = P->fused_colour && h->fuse_colour && !sel && !out_hel && !chan;
     // the operand tables of the separate colour sum of this precision
-    me::FusedColour fcol{nullptr, nullptr, 0, precision};
-    if (precision == ME_FP64) fcol = {h->d_aop64, nullptr, 0, ME_FP64};
+    me::FusedColour fcol{nullptr, nullptr, 0, precision, nullptr, 0.0, hel_per_group};
+    if (precision == ME_FP64) fcol.aop = h->d_aop64, fcol.form = ME_FP64;
     else if (precision == ME_MIXED_FP16) fcol.aop = h->d_aop16;
-    else fcol = {h->d_aopb, h->d_aopb_lo, h->lo_mask_b16, precision};
+    else fcol.aop = h->d_aopb, fcol.aop_lo = h->d_aopb_lo, fcol.lo_mask = h->lo_mask_b16;
+    // small processes: the amplitude kernel also sums the helicities (one launch)
+    const bool hsum = fused && P->hel_sum_in_kernel && n_good <= 16;
     void* jamp = scratch;
     double* part = reinterpret_cast<double*>(static_cast<char*>(scratch) + (size_t)chunk * jamp_bytes_per_event);
     for (int64_t c0 = 0; c0 < n; c0 += chunk) {
@@ -363,7 +365,17 @@ int run_chunks(me_handle* h, int precision, const signed char* hel, int n_good, 
         TimedLaunch ta(h, st, 0, timed);
         const int* ch = chan ? chan + c0 : nullptr;
         hipError_t e;
-        if (fused) {
+        if (fused && hsum) {
+            // the amplitude kernel ends with the colour sum and the helicity sum
+            fcol.hsum_out = out + c0;
+            fcol.hsum_scale = 1.0 / ((double)P->colour_den * P->avg);
+            e = fp64 ? P->launch_f64(m, nc, ld, hel, n_good, h->mt, h->g, static_cast<double*>(jamp), nullptr,
+                                     nullptr, &fcol, st)
+                     : P->launch_f32(m, nc, ld, hel, n_good, h->mt, h->g, static_cast<float*>(jamp), nullptr,
+                                     nullptr, &fcol, st);
+            ta.done();
+            if (e != hipSuccess) return fail(ME_EHIP, std::string("amplitude kernel: ") + hipGetErrorString(e));
+        } else if (fused) {
             // the amplitude kernel ends with the colour sum: D |M_h|^2 per (helicity, event) in the
             // jamp scratch, then the helicity sum in the separate kernels' order (same groups)
             e = fp64 ? P->launch_f64(m, nc, ld, hel, n_good, h->mt, h->g, static_cast<double*>(jamp), nullptr,

@@ -15,6 +15,13 @@ struct FusedColour {
     const void* aop_lo;  // BF16 lo tiles (BF16 form)
     uint64_t lo_mask;    // tiles with a non-zero lo part (BF16 form)
     int form;            // ME_FP64, ME_MIXED_FP16 or ME_MIXED_BF16 (me.h)
+    // processes with hel_sum_in_kernel: if hsum_out is set, one workgroup holds all good
+    // helicities of its event block and the kernel also sums them, in groups of hel_per_group
+    // from the first (the order of the separate helicity-sum kernel), times hsum_scale, into
+    // hsum_out[event]; nothing goes to the jamp scratch
+    double* hsum_out;
+    double hsum_scale;
+    int hel_per_group;
 };
 
 // fc: null, or the fused colour sum (then chan must be null)
@@ -47,6 +54,7 @@ struct ProcessDesc {
     int lines_per_diagram;
     int sde_supported;         // single-diagram channel weights available
     int fused_colour;          // the amplitude kernels can do the colour sum themselves (FusedColour)
+    int hel_sum_in_kernel;     // ... and the helicity sum (FusedColour.hsum_out; at most 16 good helicities)
     amp_launch_f64 launch_f64;
     amp_launch_f32 launch_f32;
 };

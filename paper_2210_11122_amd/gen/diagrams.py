@@ -280,6 +280,7 @@ def node_size(key, remat_ext=False):
     that are recomputed at each use occupy none"""
     if key[0].startswith("EXT") and (remat_ext is True or
                                      (remat_ext == "gluons" and key[0] in ("EXT_G", "EXT_ROOT")) or
+                                     (remat_ext == "gluons_lds" and key[0] == "EXT_G") or
                                      (remat_ext == "spinors" and key[0] in ("EXT_U", "EXT_V"))):
         return 0
     if key[0] == "EXT_G" or key[0] == "EXT_ROOT":
@@ -358,7 +359,7 @@ def schedule(plan, remat_ext=False, amps=None):
     return order
 
 
-def schedule_window(amps, nodes, jamp_sets, beta, window):
+def schedule_window(amps, nodes, jamp_sets, beta, window, remat_ext=False):
     """Greedy order like `schedule`, with an extra cost of `beta` per jamp of the candidate
     amplitude that is not in an LRU window of `window` jamps (jamp locality: fewer window
     evictions).  amps: [(diagram index, option, deps)]; jamp_sets[diagram] = jamp indices."""
@@ -391,7 +392,7 @@ def schedule_window(amps, nodes, jamp_sets, beta, window):
     def score(i):
         deps = amps[i][2]
         new = missing(deps)
-        add = sum(node_size(k) for k in new)
+        add = sum(node_size(k, remat_ext) for k in new)
         dec = {}
         for k in new:
             for d in node_deps(k):
@@ -403,7 +404,7 @@ def schedule_window(amps, nodes, jamp_sets, beta, window):
         for d, c in dec.items():
             total = pending[d] + (consumers[d] if d in newset else 0)
             if c >= total:
-                freed += node_size(d)
+                freed += node_size(d, remat_ext)
         miss = sum(1 for j in jamp_sets[amps[i][0]] if j not in win)
         return (add - freed + beta * miss, add)
 
@@ -478,18 +479,27 @@ def closure(deps):
     return need
 
 
-def segment_plan(plan, jamp_sets, n_segments, beta, window, amps=None):
+def segment_plan(plan, jamp_sets, n_segments, beta, window, amps=None, cut="amps", remat_ext=False):
     """Cut the jamp-aware order into n_segments contiguous pieces (one kernel each, which
     recomputes the currents it needs) and reorder each piece the same way.  amps: the units
-    to order (default: the plan's amplitudes; see `schedule`)."""
+    to order (default: the plan's amplitudes; see `schedule`).  cut: "amps" cuts where the
+    amplitudes evaluated so far (a unit counts its members) reach k / n_segments of all, so the
+    kernels share the work evenly; "units" cuts into equal numbers of units."""
     amps = plan.amplitudes() if amps is None else amps
-    order = schedule_window(amps, plan.nodes(), jamp_sets, beta, window)
-    n = len(order)
+    order = schedule_window(amps, plan.nodes(), jamp_sets, beta, window, remat_ext)
+    size = [len(u[1][1]) if (cut == "amps" and u[1][0] == "CLASS") else 1 for u in order]
+    total = sum(size)
+    cuts, acc = [0], 0
+    for i, w in enumerate(size):
+        acc += w
+        if len(cuts) < n_segments and acc * n_segments >= len(cuts) * total:
+            cuts.append(i + 1)
+    cuts += [len(order)] * (n_segments + 1 - len(cuts))
     segs = []
     for k in range(n_segments):
-        piece = order[k * n // n_segments:(k + 1) * n // n_segments]
+        piece = order[cuts[k]:cuts[k + 1]]
         need = closure([d for _, _, deps in piece for d in deps])
-        segs.append(schedule_window(piece, need, jamp_sets, beta, window))
+        segs.append(schedule_window(piece, need, jamp_sets, beta, window, remat_ext))
     return segs
 
 

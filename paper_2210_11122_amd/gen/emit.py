@@ -30,6 +30,8 @@ FLOPS = {
 QCD_PROCESSES = {"gg_tt": 2, "gg_ttg": 3, "gg_ttgg": 4, "gg_ttggg": 5}
 # name -> (segment kernels, LDS jamp-window slots, weight of window misses in the schedule)
 SEGMENTS = {"gg_ttggg": (14, 28, 1.0)}
+# how the segments are cut from the schedule (diagrams.segment_plan): "amps" or "units"
+SEGMENT_CUT = "amps"
 # sum the amplitudes of entries with proportional colour coefficients before their jamp updates
 PRESUM = True
 # sa += u a for the units u of the Gaussian integers
@@ -45,6 +47,20 @@ MIN_WAVES = {"gg_tt": (4, 5), "gg_ttg": (2, 3), "gg_ttgg": (1, 2), "gg_ttggg": (
 # name -> waves per workgroup (FP64, FP32 kernels): consecutive helicities of one 64-event block
 # that share the staged momenta (less LDS per wave where LDS, not registers, limits the waves)
 WAVES_PER_GROUP = {"gg_ttgg": (1, 2), "gg_ttggg": (2, 4)}
+# processes whose programs keep no external gluon wavefunction in registers: the workgroup
+# stages each event's gluon bases in LDS once (helas.hpp, stage_gluon_basis) and every use
+# rebuilds the polarisation vector from there.  It removes the FP64 kernels' spills but costs
+# a multiply by the helicity sign per component at each of the many uses, plus LDS reads, and
+# measured slower (gg_ttgg FP64 25.2 -> 27.4 ms per 2^19 events, with 2 / 4 waves per group to
+# keep the occupancy); off
+GLUONS_FROM_LDS = set()
+# processes with at most 16 helicity combinations whose kernel also sums the helicities: one
+# workgroup holds every good helicity of an event block (64 lanes each), and its first wave adds
+# their D |M_h|^2 from LDS after the colour sum, so one launch gives |M|^2.  Only the tiny
+# e+e- processes, where a call is bound by launches: ee_mumu at 8192 events 29.7 -> 17.8 us per
+# call; gg_tt at 2^19 was slower (2.36e9 -> 2.20e9 MEs/s FP64, 1.98e9 -> 1.68e9 mixed), its
+# 16-wave workgroups waiting for each other at the barriers
+HEL_SUM_IN_KERNEL = {"ee_mumu", "ee_mumu_z"}
 ALL_PROCESSES = ["ee_mumu", "gg_tt", "gg_ttg", "gg_ttgg", "gg_ttggg", "gg_gg", "ee_mumu_z"]
 # electroweak constants of ee -> mumu with Z exchange: M_Z, Gamma_Z, M_W [GeV]
 EW_MZ, EW_WZ, EW_MW = 91.188, 2.441404, 80.419
@@ -220,6 +236,8 @@ class Process:
             if kind == "EXT_G":
                 p = self.gpar[key[1]]
                 outg = "true" if p >= 2 else "false"
+                if remat_ext == "gluons_lds":
+                    return f"ext_vec_b<R>(GB({key[1]}), lam[{p}], {outg})", FLOPS["ext_vec"]
                 return f"ext_vec<R>(PM({p}), lam[{p}], {outg})", FLOPS["ext_vec"]
             if kind == "EXT_ROOT":
                 p = self.gpar[self.ng - 1]
@@ -235,6 +253,8 @@ class Process:
                 return True
             if remat_ext == "gluons":
                 return kind in ("EXT_G", "EXT_ROOT")
+            if remat_ext == "gluons_lds":
+                return kind == "EXT_G"
             if remat_ext == "spinors":
                 return kind in ("EXT_U", "EXT_V")
             return False
@@ -451,7 +471,8 @@ class Process:
         if jamps_in_lds is None:
             jamps_in_lds = self.nc > 6
         if remat_ext is None:
-            remat_ext = False
+            remat_ext = "gluons_lds" if self.name in GLUONS_FROM_LDS else False
+        self.remat_ext = remat_ext
         nc = self.nc
         nm = self.name
         kernels = []      # (kernel name, body lines, jamp slots in LDS, output mode)
@@ -471,7 +492,8 @@ class Process:
             jsets = [set(self.perm_index[q] for q in self.jcoef[i]) for i in range(len(self.diagrams))]
             # algorithmic count: every node once, in any order
             fl = self._emit_qcd_body([], remat_ext, order=self.units())
-            segs = D.segment_plan(self.plan, jsets, n_seg, beta, window, amps=self.units())
+            segs = D.segment_plan(self.plan, jsets, n_seg, beta, window, amps=self.units(), cut=SEGMENT_CUT,
+                                  remat_ext=remat_ext)
             self.segment_orders = segs
             self.flops_exec = 0
             partial_jamp = []
@@ -568,7 +590,7 @@ class Process:
         else:
             L.append("    if (fc && (chan || !fc->aop || (sizeof(R) == 8) != (fc->form == ME_FP64))) "
                      "return hipErrorInvalidValue;")
-            L.append("    const FusedColour none{nullptr, nullptr, 0, 0};")
+            L.append("    const FusedColour none{nullptr, nullptr, 0, 0, nullptr, 0.0, 1};")
         g64, g32 = WAVES_PER_GROUP.get(self.name, (1, 1))
         L.append(f"    constexpr int WG = sizeof(R) == 8 ? {g64} : {g32};  // waves (helicities) per workgroup")
         L.append("    int64_t blocks = ((n_evt + 63) / 64) * ((n_good + WG - 1) / WG);")
@@ -583,6 +605,13 @@ class Process:
                 L.append("        if (e != hipSuccess) return e;")
                 L.append("    }")
             else:
+                if fused and self.name in HEL_SUM_IN_KERNEL:
+                    L.append("    if (fc && fc->hsum_out) {  // one workgroup per event block, a wave per good helicity")
+                    L.append("        if (n_good > 16) return hipErrorInvalidValue;")
+                    L.append(f"        hipLaunchKernelGGL(({kname}<R, false, true>), dim3((unsigned)((n_evt + 63) / 64)), dim3(64 * n_good), 0, st, "
+                             "mom, n_evt, ld, hel, n_good, mt, gs, jamp, nullptr, nullptr, *fc);")
+                    L.append("        return hipGetLastError();")
+                    L.append("    }")
                 L.append("    if (chan)")
                 tail = ", none" if fused else ""
                 L.append(f"        hipLaunchKernelGGL(({kname}<R, true>), dim3((unsigned)blocks), dim3(64 * WG), 0, st, mom, n_evt, "
@@ -605,7 +634,8 @@ class Process:
         L.append(f"        proc_{nm}::colour_num, {self.cden}, proc_{nm}::final_massive, proc_{nm}::orderings, "
                  f"{n_order},")
         L.append(f"        {self.n_diagrams}, {self.n_amplitudes}, {fl}.0, {self.flops_exec}.0, proc_{nm}::NSLOT,")
-        L.append(f"        proc_{nm}::diagram_lines, {nlines}, {0 if self.lines is None else 1}, {1 if fused else 0},")
+        L.append(f"        proc_{nm}::diagram_lines, {nlines}, {0 if self.lines is None else 1}, {1 if fused else 0}, "
+                 f"{1 if fused and nm in HEL_SUM_IN_KERNEL else 0},")
         L.append(f"        proc_{nm}::launch<double>, proc_{nm}::launch<float>,")
         L.append("    };")
         L.append("    return &d;")
@@ -623,13 +653,20 @@ class Process:
         into sde[h][0/1][column]; `first` is false for segment kernels that add to the
         sums of the segments before them."""
         L = []
-        L.append("template <class R, bool SDE>")
+        hsum = fused and self.name in HEL_SUM_IN_KERNEL
+        # HS: the instance that also sums the helicities (its workgroup holds an event block's
+        # good helicities; the LDS it needs for that is only in this instance)
+        L.append("template <class R, bool SDE, bool HS = false>" if hsum else "template <class R, bool SDE>")
         w64, w32 = MIN_WAVES.get(self.name, (1, 1))
         g64, g32 = WAVES_PER_GROUP.get(self.name, (1, 1))
         if (g64, g32) != (1, 1) and not (jamps_in_lds or mode == "slots"):
             # register jamps are staged in the (shared) momentum area for the colour sum
             raise ValueError("several waves per workgroup need per-wave LDS jamps")
+        if hsum and (g64, g32) != (1, 1):
+            raise ValueError("the helicity sum in the kernel sizes the workgroup by the good helicities")
         threads = "64" if (g64, g32) == (1, 1) else f"64 * (sizeof(R) == 8 ? {g64} : {g32})"
+        if hsum:
+            threads = "1024"   # up to 16 helicity waves of one event block
         bounds = threads if (w64, w32) == (1, 1) else f"{threads}, (sizeof(R) == 8 ? {w64} : {w32})"
         L.append(f"__global__ __launch_bounds__({bounds}) void {kname}(const double* __restrict__ mom, int64_t n_evt, "
                  "int64_t ld, const signed char* __restrict__ hel, int n_good, double mt, double gs, "
@@ -640,14 +677,33 @@ class Process:
         L.append("    __shared__ double lds[4 * NPAR * 64];")
         L.append("    const int lane = threadIdx.x & 63;")
         L.append("    const int64_t w = xcd_remap(blockIdx.x, gridDim.x);")
-        L.append("    const int hpb = (n_good + WG - 1) / WG;  // workgroups per event block")
+        if hsum:
+            L.append("    // with the helicity sum here, one workgroup holds all good helicities of its block")
+            L.append("    constexpr bool hsum = HS && !SDE;")
+            L.append("    const int wg = hsum ? n_good : WG;")
+            L.append("    const int hpb = (n_good + wg - 1) / wg;  // workgroups per event block")
+        else:
+            L.append("    const int hpb = (n_good + WG - 1) / WG;  // workgroups per event block")
         L.append("    const int64_t e0 = (w / hpb) * 64;")
-        L.append("    const int hr = (int)(w % hpb) * WG + (int)(threadIdx.x >> 6);")
+        L.append(f"    const int hr = (int)(w % hpb) * {'wg' if hsum else 'WG'} + (int)(threadIdx.x >> 6);")
         L.append("    const bool live = hr < n_good;  // a spare wave of the last group repeats a helicity, writes nothing")
         L.append("    const int h = live ? hr : n_good - 1;")
         L.append("    const int64_t e = e0 + lane;  // < ld: ld is a multiple of 64 covering the grid")
-        L.append("    stage_momenta<NPAR, WG>(mom, n_evt, e0, lds, threadIdx.x);")
+        if hsum:
+            L.append("    if constexpr (hsum)")
+            L.append("        stage_momenta_n<NPAR>(mom, n_evt, e0, lds, threadIdx.x, 64 * wg);")
+            L.append("    else")
+            L.append("        stage_momenta<NPAR, WG>(mom, n_evt, e0, lds, threadIdx.x);")
+        else:
+            L.append("    stage_momenta<NPAR, WG>(mom, n_evt, e0, lds, threadIdx.x);")
         L.append("#define PM(i) lds_p4(lds, i, lane)")
+        if getattr(self, "remat_ext", False) == "gluons_lds":
+            gp = ", ".join(str(p) for p in self.gpar)
+            L.append(f"    // the gluons' polarisation bases, for every helicity wave of the block")
+            L.append(f"    constexpr int GPART[{len(self.gpar)}] = {{{gp}}};")
+            L.append(f"    __shared__ R gbl[6 * {len(self.gpar)} * 64];")
+            L.append(f"    stage_gluon_basis<R, {len(self.gpar)}, WG>(lds, gbl, GPART, threadIdx.x);")
+            L.append("#define GB(j) lds_gb<R>(gbl, j, lane)")
         L.append("    int lam[NPAR];")
         L.append("#pragma unroll")
         L.append("    for (int i = 0; i < NPAR; ++i) lam[i] = hel[h * NPAR + i];")
@@ -717,10 +773,18 @@ class Process:
                     src = "Jl"
                     L.append("        __syncthreads();  // every jamp update of the wave has completed")
                 else:
-                    # register jamps go to the momentum area of LDS, which is no longer read
+                    # register jamps go to the momentum area of LDS, which is no longer read (with
+                    # the helicity sum here: an area per wave)
                     src = "Js"
                     L.append("        __syncthreads();")
-                    L.append("        R* Js = reinterpret_cast<R*>(lds);")
+                    if hsum:
+                        L.append("        R* Js = reinterpret_cast<R*>(lds);")
+                        L.append("        if constexpr (hsum) {")
+                        L.append("            __shared__ R Jst[16 * 2 * NC * 64];")
+                        L.append("            Js = Jst + (threadIdx.x >> 6) * (2 * NC * 64);")
+                        L.append("        }")
+                    else:
+                        L.append("        R* Js = reinterpret_cast<R*>(lds);")
                     L.append("#pragma unroll")
                     L.append("        for (int s = 0; s < 2 * NC; ++s) Js[s * 64 + lane] = Jr[s];")
                     L.append("        __syncthreads();")
@@ -733,6 +797,23 @@ class Process:
                 L.append("        else")
                 L.append(f"            me_h = colour_sum_lds_h16<NC, Fp16Terms>({src}, static_cast<const _Float16*>(fc.aop), "
                          "static_cast<const _Float16*>(fc.aop), 0, lane);")
+                if hsum:
+                    L.append("        if constexpr (hsum) {  // the helicity sum: the separate kernel's groups and order")
+                    L.append("            __shared__ double red[16 * 64];")
+                    L.append("            red[hr * 64 + lane] = me_h;")
+                    L.append("            __syncthreads();")
+                    L.append("            if (threadIdx.x < 64 && e < n_evt) {")
+                    L.append("                double s = 0.0;")
+                    L.append("                for (int h0 = 0; h0 < n_good; h0 += fc.hel_per_group) {")
+                    L.append("                    const int h1 = min(n_good, h0 + fc.hel_per_group);")
+                    L.append("                    double m = 0.0;")
+                    L.append("                    for (int k = h0; k < h1; ++k) m += red[k * 64 + lane];")
+                    L.append("                    s += m;")
+                    L.append("                }")
+                    L.append("                fc.hsum_out[e] = s * fc.hsum_scale;")
+                    L.append("            }")
+                    L.append("            return;")
+                    L.append("        }")
                 L.append("        if (live && e < n_evt) reinterpret_cast<double*>(jamp)[(int64_t)h * n_evt + e] = me_h;")
                 L.append("        return;")
                 L.append("    }")
@@ -748,7 +829,7 @@ class Process:
             L.append("#pragma unroll")
             L.append("        for (int s = 0; s < 2 * NC; ++s) o[s * ld] = jo[s];")
             L.append("    }")
-        for m in ("PM", "JADD", "JGET", "JZERO", "JTAKE", "JLAST", "JPUT", "SDEACC"):
+        for m in ("PM", "GB", "JADD", "JGET", "JZERO", "JTAKE", "JLAST", "JPUT", "SDEACC"):
             L.append(f"#undef {m}")
         L.append("}")
         return L
@@ -791,29 +872,36 @@ NOT_EMITTED = set()
 
 
 _PM = re.compile(r"PM\((\d+)\)")
+_GB = re.compile(r"GB\((\d+)\)")
 
 
 def _pipeline_momenta(lines, marks, puts=None):
-    """Rewrite a diagram program so that the momenta of amplitude step s are read from LDS
-    into registers (const P4 m<s>_<i>) at one point: before the amplitude of step s-1
-    (step 0: at its start).  marks[s] = (first node line, amplitude line, first jamp-update
-    line) of step s, indices into lines.  puts[s] (window programs): the partial-slot stores
-    of the slots step s evicted, placed after the amplitude of step s+1 (the caller places
-    those of the last step)."""
+    """Rewrite a diagram program so that the LDS reads of amplitude step s (momenta PM(i),
+    gluon bases GB(j)) land in registers (const P4 m<s>_<i>, GB g<s>_<j>) at one point: before
+    the amplitude of step s-1 (step 0: at its start).  marks[s] = (first node line, amplitude
+    line, first jamp-update line) of step s, indices into lines.  puts[s] (window programs): the
+    partial-slot stores of the slots step s evicted, placed after the amplitude of step s+1 (the
+    caller places those of the last step)."""
     out = []
     used = []
     for s, (a, b, c) in enumerate(marks):
         ks = sorted({int(k) for ln in lines[a:c] for k in _PM.findall(ln)})
-        used.append(ks)
+        gs = sorted({int(k) for ln in lines[a:c] for k in _GB.findall(ln)})
+        used.append((ks, gs))
 
     def decl(s):
-        return [f"    P4 m{s}_{k} = PM({k});" for k in used[s]]
+        ks, gs = used[s]
+        return [f"    P4 m{s}_{k} = PM({k});" for k in ks] + [f"    GBT<R> g{s}_{k} = GB({k});" for k in gs]
 
     def pin(s):
-        return [f"    pin_p4<R>(m{s}_{k});" for k in used[s]] if PIN_MOMENTA else []
+        if not PIN_MOMENTA:
+            return []
+        ks, gs = used[s]
+        return [f"    pin_p4<R>(m{s}_{k});" for k in ks] + [f"    pin_gb<R>(g{s}_{k});" for k in gs]
 
     def sub(s, ln):
-        return _PM.sub(lambda m: f"m{s}_{m.group(1)}", ln)
+        ln = _PM.sub(lambda m: f"m{s}_{m.group(1)}", ln)
+        return _GB.sub(lambda m: f"g{s}_{m.group(1)}", ln)
 
     pos = 0
     for s, (a, b, c) in enumerate(marks):

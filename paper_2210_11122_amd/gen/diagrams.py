@@ -503,25 +503,50 @@ def segment_plan(plan, jamp_sets, n_segments, beta, window, amps=None, cut="amps
     return segs
 
 
-def window_program(order, jamp_sets, window):
-    """Static LRU allocation of jamps to `window` slots along `order`.  Returns, per
-    amplitude, [(jamp, slot, flush)] where flush is None or (slot, partial index, jamp)
-    to write out before the slot is reused, plus the final flushes and the jamp of every
-    partial slot."""
+def window_program(order, jamp_sets, window, policy="opt"):
+    """Static allocation of jamps to `window` slots along `order`.  Returns, per amplitude,
+    [(jamp, slot, flush)] where flush is None or (slot, partial index, jamp) to write out
+    before the slot is reused, plus the final flushes and the jamp of every partial slot.
+    policy: when a slot must be freed, "opt" evicts the jamp whose next use lies furthest ahead
+    (or never comes), which the static order makes known (Belady's optimal replacement);
+    "lru" the least recently used."""
     import collections
-    win = collections.OrderedDict()   # jamp -> slot
+    seq = [sorted(jamp_sets[u[0]]) for u in order]
+    uses = collections.defaultdict(list)
+    for i, js in enumerate(seq):
+        for j in js:
+            uses[j].append(i)
+
+    def next_use(j, i):
+        """first step after step i that uses jamp j"""
+        lst = uses[j]
+        lo, hi = 0, len(lst)
+        while lo < hi:
+            mid = (lo + hi) // 2
+            if lst[mid] <= i:
+                lo = mid + 1
+            else:
+                hi = mid
+        return lst[lo] if lo < len(lst) else len(seq)
+
+    win = collections.OrderedDict()   # jamp -> slot, least recently used first
     free = list(range(window))[::-1]
     partial_jamp = []
     steps = []
-    for di, _, _ in order:
+    for i, js in enumerate(seq):
         ops = []
-        for j in sorted(jamp_sets[di]):
+        for j in js:
             flush = None
             if j in win:
                 win.move_to_end(j)
             else:
                 if not free:
-                    jj, s = win.popitem(last=False)
+                    if policy == "lru":
+                        jj = next(iter(win))
+                    else:
+                        cand = [x for x in win if x not in js]
+                        jj = max(cand, key=lambda x: (next_use(x, i), -list(win).index(x)))
+                    s = win.pop(jj)
                     flush = (s, len(partial_jamp), jj)
                     partial_jamp.append(jj)
                     free.append(s)

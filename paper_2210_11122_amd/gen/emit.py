@@ -29,7 +29,7 @@ FLOPS = {
 
 QCD_PROCESSES = {"gg_tt": 2, "gg_ttg": 3, "gg_ttgg": 4, "gg_ttggg": 5}
 # name -> (segment kernels, LDS jamp-window slots, weight of window misses in the schedule)
-SEGMENTS = {"gg_ttggg": (14, 28, 1.0)}
+SEGMENTS = {"gg_ttggg": (14, 35, 2.0)}
 # how the segments are cut from the schedule (diagrams.segment_plan): "amps" or "units"
 SEGMENT_CUT = "amps"
 # sum the amplitudes of entries with proportional colour coefficients before their jamp updates
@@ -46,7 +46,7 @@ PIN_MOMENTA = True
 MIN_WAVES = {"gg_tt": (4, 5), "gg_ttg": (2, 3), "gg_ttgg": (1, 2), "gg_ttggg": (1, 2)}
 # name -> waves per workgroup (FP64, FP32 kernels): consecutive helicities of one 64-event block
 # that share the staged momenta (less LDS per wave where LDS, not registers, limits the waves)
-WAVES_PER_GROUP = {"gg_ttgg": (1, 2), "gg_ttggg": (2, 4)}
+WAVES_PER_GROUP = {"gg_ttgg": (1, 2), "gg_ttggg": (4, 8)}
 # processes whose programs keep no external gluon wavefunction in registers: the workgroup
 # stages each event's gluon bases in LDS once (helas.hpp, stage_gluon_basis) and every use
 # rebuilds the polarisation vector from there.  It removes the FP64 kernels' spills but costs

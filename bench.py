@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 # the paper's FP64 figure for this exact workload (Table 2: V100, gg->ttgg, grid 524288); context only
 PAPER_FP64_MES = 4.20e5
 FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+HBM_PEAK_GBS = 8000.0           # HBM3E, published peak
 FP32_VALU_PEAK_TFLOPS = 78.6   # same without packed FP32 (disabled in this build)
 MFMA_F64_PEAK_TFLOPS = 78.6
 MFMA_F16_PEAK_TFLOPS = 2500.0
@@ -175,8 +176,9 @@ def process_table(torch, min_ms=500.0, threads=None):
     from tests import workloads as W
     threads = threads or hostinfo.host_threads()
     rows = []
-    for name in W.ALL:
-        n = W.PROCESSES[name][2]
+    # every process at its configured size; ee_mumu also at 2^20, where its calls are long enough
+    # to be set by HBM rather than by launches
+    for name, n in [(nm, W.PROCESSES[nm][2]) for nm in W.ALL] + [("ee_mumu", 1 << 20)]:
         rs = W.sqrt_s(name)
         row = {"process": name, "n_events": n}
         ref = None
@@ -199,7 +201,8 @@ def process_table(torch, min_ms=500.0, threads=None):
             for _ in range(2):
                 proc.sigma(x, out=y)
             torch.cuda.synchronize()
-            proc.profile(True)
+            # per-call times without the library's per-launch events (which add host work
+            # before each launch, a visible share of the small processes' calls) ...
             times, spent = [], 0.0
             while len(times) < 5 or (spent < min_ms and len(times) < 200):
                 a = torch.cuda.Event(enable_timing=True)
@@ -210,13 +213,20 @@ def process_table(torch, min_ms=500.0, threads=None):
                 b.synchronize()
                 times.append(a.elapsed_time(b))
                 spent += times[-1]
+            # ... then the amplitude kernel's own time over as many calls
+            proc.profile(True)
+            for _ in range(len(times)):
+                proc.sigma(x, out=y)
+            torch.cuda.synchronize()
             ms_amp, ms_cs, n_amp, _ = proc.profile(False)
             med = float(np.median(times))
             lanes = n * info["n_good_hel"]
             f_amp = info["flops_amp_lane"] + (info["flops_colour_lane"] if info["fused_colour"] else 0.0)
             f_me = info["n_good_hel"] * (info["flops_amp_lane"] + info["flops_colour_lane"])
             mes = n / med * 1e3
+            bytes_me = x.shape[1] * 32 + 8   # momenta in, |M|^2 out
             r = {"MEs_per_s": mes, "ms_per_call": med, "calls": len(times),
+                 "hbm_bytes_per_me": bytes_me, "hbm_frac": mes * bytes_me / (HBM_PEAK_GBS * 1e9),
                  "amp_kernel_tflops": f_amp * lanes * len(times) / (ms_amp / 1e3) / 1e12 if ms_amp > 0 else None,
                  "end_to_end_tflops": mes * f_me / 1e12,
                  "flops_per_me": f_me, "colour_sum_in_amp_kernel": bool(info["fused_colour"]),
@@ -242,9 +252,9 @@ def process_table(torch, min_ms=500.0, threads=None):
 def table_markdown(rows):
     def f(v, k=3):
         return "-" if v is None else f"{v:.{k}g}"
-    L = ["| process | events | form | MEs/s | amp. kernel TFLOP/s (frac of 78.6) | end-to-end frac | "
+    L = ["| process | events | form | MEs/s | amp. kernel TFLOP/s (frac of 78.6) | end-to-end frac | HBM frac | "
          "rel. err vs FP64 oracle (max / median / p99 / p99.9; n) | vs GPU FP64, full batch (max / median) |",
-         "|---|---|---|---|---|---|---|---|"]
+         "|---|---|---|---|---|---|---|---|---|"]
     for row in rows:
         for prec in ("fp64", "mixed_fp16", "mixed_bf16"):
             r = row[prec]
@@ -252,12 +262,17 @@ def table_markdown(rows):
             g = r.get("rel_err_vs_gpu_fp64_full_batch")
             L.append(f"| {row['process']} | {row['n_events']} | {prec} | {f(r['MEs_per_s'], 4)} | "
                      f"{f(r['amp_kernel_tflops'])} ({f(r['amp_kernel_frac'], 2)}) | {f(r['end_to_end_frac'], 2)} | "
+                     f"{f(r['hbm_frac'], 2)} | "
                      f"{f(e['max'], 2)} / {f(e['median'], 2)} / {f(e['p99'], 2)} / {f(e['p999'], 2)}; {e['n']} | "
                      + (f"{f(g['max'], 2)} / {f(g['median'], 2)} |" if g else "- |"))
     L.append("")
     L.append("| process | oracle MEs/s (threads) | oracle MEs/s, 1 thread |")
     L.append("|---|---|---|")
+    seen = set()
     for row in rows:
+        if row["process"] in seen:
+            continue
+        seen.add(row["process"])
         o = row["oracle"]
         L.append(f"| {row['process']} | {f(o['MEs_per_s'], 4)} ({o['threads']}) | {f(o['MEs_per_s_single_thread'], 4)} |")
     return "\n".join(L) + "\n"
@@ -380,6 +395,23 @@ def main():
             "ms_per_step": ms_cs / args.steps,
         }),
     }
+
+    # bytes the path must move per ME: the event's momenta in, |M|^2 out
+    bytes_me = x.shape[1] * 32 + 8
+    amp_bytes_launch = bytes_me * n_evt / max(amp_launches_per_step, 1)
+    hbm_launch = amp_bytes_launch / (result["roofline"]["avg_launch_ms"] / 1e3) / 1e9
+    result["hbm"] = {"bytes_per_me": bytes_me,
+                     "per_call_GBs": mes64 * bytes_me / 1e9, "per_call_frac": mes64 * bytes_me / (HBM_PEAK_GBS * 1e9),
+                     "amp_kernel_GBs": hbm_launch, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    flops_me = info["n_good_hel"] * (info["flops_amp_lane"] + info["flops_colour_lane"])
+    if bytes_me / (HBM_PEAK_GBS * 1e9) > flops_me / (FP64_VALU_PEAK_TFLOPS * 1e12):
+        # fewer flops per byte than the machine balance (ee_mumu): HBM sets the roofline
+        rf = result["roofline"]
+        rf.update({"bound": "hbm", "kernel": rf["kernel"] + "; algorithmic bytes: momenta in, |M|^2 out",
+                   "achieved": hbm_launch, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                   "frac": hbm_launch / HBM_PEAK_GBS, "bytes_per_launch": amp_bytes_launch,
+                   "alu_TFLOPs": achieved_tflops})
+        del rf["flops_per_launch"]
 
     if info["n_partial_slots"] > 0 and n_evt > info["chunk_events"]:
         # chunks alternate between two streams, so two amplitude launches share the GPU and each

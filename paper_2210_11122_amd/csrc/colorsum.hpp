@@ -94,6 +94,17 @@ __device__ __forceinline__ void cs_store(double me, int64_t e, int64_t n_evt, do
         part[(int64_t)blockIdx.y * n_evt + e] = me;
 }
 
+// One colour flow (the e+e- processes): D |M_h|^2 = Chat_00 (Re J^2 + Im J^2), a scalar, with
+// one rounding sequence wherever it is formed (the colour-sum kernel, the amplitude kernels
+// that do the colour sum themselves); the empty asm keeps the compiler from fusing the last
+// multiply into a later addition.  c00 = aop[0], the one operand of the 1x1 table.
+__device__ __forceinline__ double cs1(double jr, double ji, double c00)
+{
+    double v = c00 * __builtin_fma(jr, jr, ji * ji);
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 // One (16-event tile, helicity) column block of the FP64 form: returns this lane's share of
 // D * |M_h|^2 for event column i (the four lane groups' shares add up to it).  load(c, ri) gives
 // the jamp of colour c (re/im) of this lane's column.  A: the tile operands in registers when
@@ -101,6 +112,10 @@ __device__ __forceinline__ void cs_store(double me, int64_t e, int64_t n_evt, do
 template <int NC, bool AREG, class Load>
 __device__ __forceinline__ double cs64_column(const Load& load, const double* A, const double* aop, int lane)
 {
+    if constexpr (NC == 1) {
+        // no tile for a 1x1 matrix: lane group 0 holds the whole value
+        return (lane >> 4) == 0 ? cs1((double)load(0, 0), (double)load(0, 1), aop[0]) : 0.0;
+    }
     constexpr int MT = (NC + 15) / 16, KT = (NC + 3) / 4;
     // the real/imaginary loop stays rolled for the large matrices (register pressure)
     constexpr int RI_UNROLL = NC > 24 ? 1 : 2;

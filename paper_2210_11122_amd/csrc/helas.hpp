@@ -570,6 +570,40 @@ __device__ __forceinline__ void pin_p4(P4& p)
 {
     if constexpr (sizeof(R) == 8) asm volatile("" : "+v"(p.t), "+v"(p.x), "+v"(p.y), "+v"(p.z));
 }
+// An external wavefunction kept in LDS, private to its lane, instead of in registers across
+// the program: slot k holds component pairs (re, im) at xw[(4 k + m) * 64 + lane] (one 16-byte
+// pair per lane in FP64, so a read is conflict-free).  ld_w4 re-reads it at every use
+// (volatile, as lds_p4).
+template <class R>
+__device__ __forceinline__ void st_w4(R* xw, int k, int lane, const W4<R>& w)
+{
+    typedef R v2 __attribute__((ext_vector_type(2)));
+    v2* p = reinterpret_cast<v2*>(xw);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) p[(4 * k + m) * 64 + lane] = {w.c[m].r, w.c[m].i};
+}
+template <class R>
+__device__ __forceinline__ W4<R> ld_w4(const R* xw, int k, int lane)
+{
+    typedef R v2 __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(3))) const volatile v2 lds_v2;
+    lds_v2* v = (lds_v2*)xw;
+    W4<R> w;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const v2 t = v[(4 * k + m) * 64 + lane];
+        w.c[m] = {t.x, t.y};
+    }
+    return w;
+}
+// as pin_p4, for an external wavefunction read ahead of the step that needs it
+template <class R>
+__device__ __forceinline__ void pin_w4(W4<R>& w)
+{
+    if constexpr (sizeof(R) == 8)
+        asm volatile("" : "+v"(w.c[0].r), "+v"(w.c[0].i), "+v"(w.c[1].r), "+v"(w.c[1].i), "+v"(w.c[2].r),
+                     "+v"(w.c[2].i), "+v"(w.c[3].r), "+v"(w.c[3].i));
+}
 // Makes an amplitude's value opaque once computed: the operations that produce it cannot be
 // fused with those that consume it, so every instance of a kernel (with or without the
 // channel-weight sums, whose extra uses of the value change what the compiler may contract)

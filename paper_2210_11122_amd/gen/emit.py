@@ -46,7 +46,7 @@ PIN_MOMENTA = True
 MIN_WAVES = {"gg_tt": (4, 5), "gg_ttg": (2, 3), "gg_ttgg": (1, 2), "gg_ttggg": (1, 2)}
 # name -> waves per workgroup (FP64, FP32 kernels): consecutive helicities of one 64-event block
 # that share the staged momenta (less LDS per wave where LDS, not registers, limits the waves)
-WAVES_PER_GROUP = {"gg_ttgg": (1, 2), "gg_ttggg": (4, 8)}
+WAVES_PER_GROUP = {"gg_ttgg": (4, 2), "gg_ttggg": (4, 8)}
 # processes whose programs keep no external gluon wavefunction in registers: the workgroup
 # stages each event's gluon bases in LDS once (helas.hpp, stage_gluon_basis) and every use
 # rebuilds the polarisation vector from there.  It removes the FP64 kernels' spills but costs
@@ -54,6 +54,18 @@ WAVES_PER_GROUP = {"gg_ttgg": (1, 2), "gg_ttggg": (4, 8)}
 # measured slower (gg_ttgg FP64 25.2 -> 27.4 ms per 2^19 events, with 2 / 4 waves per group to
 # keep the occupancy); off
 GLUONS_FROM_LDS = set()
+# name -> kinds of external wavefunctions ("EXT_U", "EXT_V", "EXT_G", or "EXT_G:<j>" for gluon j)
+# that the FP64 kernel keeps
+# in LDS, private to each lane, instead of in registers across the program: computed once,
+# read ahead of each step that uses them (as the momenta); the FP32 kernels keep them in
+# registers.  Only for processes without segment kernels.  gg_ttgg: the top spinors, 4 KB per
+# wave each, room made by four FP64 waves per workgroup sharing the staged momenta (143 KB per
+# workgroup, one per CU); per 2^19 events 24.89 -> 24.17 ms (four waves alone: 24.59 ms; a third
+# slot, a gluon, removes every scratch spill but measured 24.8 ms)
+EXT_IN_LDS = {"gg_ttgg": ("EXT_U", "EXT_V")}
+# read those ahead of the step that uses them (else at each use), and pin the copies
+PREFETCH_EXT = True
+PIN_EXT = True
 # processes with at most 16 helicity combinations whose kernel also sums the helicities: one
 # workgroup holds every good helicity of an event block (64 lanes each), and its first wave adds
 # their D |M_h|^2 from LDS after the colour sum, so one launch gives |M|^2.  Only the tiny
@@ -255,6 +267,10 @@ class Process:
             return "ext_v<R>(PM(3), mt, lam[3])", FLOPS["ext_spinor"]
 
         counted = set()
+        # external wavefunctions kept in LDS: slot of each, and the code that computes it
+        ext_lds = () if self.segments else EXT_IN_LDS.get(self.name, ())
+        xslot = {}
+        self.xw_init = []
 
         def remat(kind):
             if remat_ext is True:
@@ -269,6 +285,13 @@ class Process:
 
         def emit(key):
             kind = key[0]
+            if kind in ext_lds or (len(key) > 1 and f"{kind}:{key[1]}" in ext_lds):
+                if key not in xslot:
+                    code, fl = ext_code(key)
+                    xslot[key] = len(self.xw_init)
+                    self.xw_init.append(code)
+                    flops[0] += fl
+                return f"XW({xslot[key]})"
             if kind.startswith("EXT") and remat(kind):
                 code, fl = ext_code(key)
                 if key not in counted:
@@ -724,6 +747,17 @@ class Process:
         L.append("    int lam[NPAR];")
         L.append("#pragma unroll")
         L.append("    for (int i = 0; i < NPAR; ++i) lam[i] = hel[h * NPAR + i];")
+        xw_init = getattr(self, "xw_init", [])
+        if xw_init:
+            nx = len(xw_init)
+            L.append(f"    // {nx} external wavefunctions: in LDS, private to the lane (FP64), or in registers (FP32)")
+            L.append(f"    __shared__ R xw_wg[sizeof(R) == 8 ? WG * {nx} * 8 * 64 : 1];")
+            L.append(f"    R* const xw = xw_wg + (sizeof(R) == 8 ? (threadIdx.x >> 6) * ({nx} * 8 * 64) : 0);")
+            L.append(f"    [[maybe_unused]] W4<R> xwr[{nx}];")
+            for k, code in enumerate(xw_init):
+                L.append(f"    {{ const W4<R> t = {code}; if constexpr (sizeof(R) == 8) st_w4<R>(xw, {k}, lane, t); "
+                         f"else xwr[{k}] = t; }}")
+            L.append("#define XW(k) (sizeof(R) == 8 ? ld_w4<R>(xw, k, lane) : xwr[k])")
         L.append(f"    constexpr int NW = {nwin};")
         if jamps_in_lds or mode == "slots":
             acc = "double" if jamp_mode == "atomic64" else "R"
@@ -846,7 +880,7 @@ class Process:
             L.append("#pragma unroll")
             L.append("        for (int s = 0; s < 2 * NC; ++s) o[s * ld] = jo[s];")
             L.append("    }")
-        for m in ("PM", "GB", "JADD", "JGET", "JZERO", "JTAKE", "JLAST", "JPUT", "SDEACC"):
+        for m in ("PM", "GB", "XW", "JADD", "JGET", "JZERO", "JTAKE", "JLAST", "JPUT", "SDEACC"):
             L.append(f"#undef {m}")
         L.append("}")
         return L
@@ -938,6 +972,7 @@ NOT_EMITTED = set()
 
 _PM = re.compile(r"PM\((\d+)\)")
 _GB = re.compile(r"GB\((\d+)\)")
+_XW = re.compile(r"XW\((\d+)\)")
 
 
 def _pipeline_momenta(lines, marks, puts=None):
@@ -952,20 +987,25 @@ def _pipeline_momenta(lines, marks, puts=None):
     for s, (a, b, c) in enumerate(marks):
         ks = sorted({int(k) for ln in lines[a:c] for k in _PM.findall(ln)})
         gs = sorted({int(k) for ln in lines[a:c] for k in _GB.findall(ln)})
-        used.append((ks, gs))
+        xs = sorted({int(k) for ln in lines[a:c] for k in _XW.findall(ln)}) if PREFETCH_EXT else []
+        used.append((ks, gs, xs))
 
     def decl(s):
-        ks, gs = used[s]
-        return [f"    P4 m{s}_{k} = PM({k});" for k in ks] + [f"    GBT<R> g{s}_{k} = GB({k});" for k in gs]
+        ks, gs, xs = used[s]
+        return ([f"    P4 m{s}_{k} = PM({k});" for k in ks] + [f"    GBT<R> g{s}_{k} = GB({k});" for k in gs]
+                + [f"    W4<R> y{s}_{k} = XW({k});" for k in xs])
 
     def pin(s):
         if not PIN_MOMENTA:
             return []
-        ks, gs = used[s]
-        return [f"    pin_p4<R>(m{s}_{k});" for k in ks] + [f"    pin_gb<R>(g{s}_{k});" for k in gs]
+        ks, gs, xs = used[s]
+        return ([f"    pin_p4<R>(m{s}_{k});" for k in ks] + [f"    pin_gb<R>(g{s}_{k});" for k in gs]
+                + ([f"    pin_w4<R>(y{s}_{k});" for k in xs] if PIN_EXT else []))
 
     def sub(s, ln):
         ln = _PM.sub(lambda m: f"m{s}_{m.group(1)}", ln)
+        if PREFETCH_EXT:
+            ln = _XW.sub(lambda m: f"y{s}_{m.group(1)}", ln)
         return _GB.sub(lambda m: f"g{s}_{m.group(1)}", ln)
 
     pos = 0

@@ -127,13 +127,17 @@ def test_every_diagram_evaluated_once(name):
     src = P.source()
     assert len(re.findall(r"^\s+a = amp_", src, re.M)) == P.n_amplitudes
     # every node of the plan computed exactly once; external gluons of programs that take them
-    # from the LDS bases are rebuilt at each use instead
+    # from the LDS bases are rebuilt at each use instead; external wavefunctions kept in LDS
+    # per lane are computed once at the start (one store each) and read at their uses
     names = re.findall(r"const W4<R> (w\d+) =", src)
+    kept = re.findall(r"st_w4<R>\(xw, (\d+), lane, t\)", src)
+    assert len(kept) == len(set(kept)) == len(P.xw_init) >= len(emit.EXT_IN_LDS.get(name, ()))
+    assert all(f"XW({k})" in src for k in kept)
     nodes = P.plan.nodes()
     if name in emit.GLUONS_FROM_LDS:
         nodes = {k for k in nodes if k[0] != "EXT_G"}
         assert "ext_vec<" not in src and len(re.findall(r"ext_vec_b<R>\(g\d+_\d+, lam\[\d\], ", src)) > 0
-    assert len(names) == len(set(names)) == len(nodes)
+    assert len(names) == len(set(names)) and len(names) + len(kept) == len(nodes)
 
 
 def test_plan_covers_every_diagram_with_its_own_subdiagrams():

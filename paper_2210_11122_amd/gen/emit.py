@@ -46,7 +46,7 @@ PIN_MOMENTA = True
 MIN_WAVES = {"gg_tt": (4, 5), "gg_ttg": (2, 3), "gg_ttgg": (1, 2), "gg_ttggg": (1, 2)}
 # name -> waves per workgroup (FP64, FP32 kernels): consecutive helicities of one 64-event block
 # that share the staged momenta (less LDS per wave where LDS, not registers, limits the waves)
-WAVES_PER_GROUP = {"gg_ttgg": (4, 2), "gg_ttggg": (4, 8)}
+WAVES_PER_GROUP = {"gg_ttgg": (4, 4), "gg_ttggg": (4, 8)}
 # processes whose programs keep no external gluon wavefunction in registers: the workgroup
 # stages each event's gluon bases in LDS once (helas.hpp, stage_gluon_basis) and every use
 # rebuilds the polarisation vector from there.  It removes the FP64 kernels' spills but costs
@@ -54,15 +54,20 @@ WAVES_PER_GROUP = {"gg_ttgg": (4, 2), "gg_ttggg": (4, 8)}
 # measured slower (gg_ttgg FP64 25.2 -> 27.4 ms per 2^19 events, with 2 / 4 waves per group to
 # keep the occupancy); off
 GLUONS_FROM_LDS = set()
-# name -> kinds of external wavefunctions ("EXT_U", "EXT_V", "EXT_G", or "EXT_G:<j>" for gluon j)
-# that the FP64 kernel keeps
-# in LDS, private to each lane, instead of in registers across the program: computed once,
-# read ahead of each step that uses them (as the momenta); the FP32 kernels keep them in
-# registers.  Only for processes without segment kernels.  gg_ttgg: the top spinors, 4 KB per
-# wave each, room made by four FP64 waves per workgroup sharing the staged momenta (143 KB per
-# workgroup, one per CU); per 2^19 events 24.89 -> 24.17 ms (four waves alone: 24.59 ms; a third
-# slot, a gluon, removes every scratch spill but measured 24.8 ms)
-EXT_IN_LDS = {"gg_ttgg": ("EXT_U", "EXT_V")}
+# name -> (FP64 kernel, FP32 kernel): the external wavefunctions ("EXT_U", "EXT_V", "EXT_G", or
+# "EXT_G:<j>" for gluon j) that the kernel keeps in LDS, private to each lane, instead of in
+# registers across the program: computed once, read ahead of each step that uses them (as the
+# momenta).  Only for processes without segment kernels.
+# * gg_ttgg FP64: the top spinors, 4 KB per wave each, room made by four waves per workgroup
+#   sharing the staged momenta (143 KB per workgroup, one per CU); per 2^19 events 24.89 -> 24.17
+#   ms (four waves alone: 24.59 ms; a third slot, a gluon, removes every scratch spill but
+#   measured 24.8 ms).
+# * gg_ttgg FP32: the same two, 2 KB per wave each, with four waves per workgroup (78 KB, two per
+#   CU); per 2^19 events 14.54 -> 14.20 ms (four waves alone: 14.33 ms; one spinor: 14.45 ms).
+# * gg_ttg FP64: the top spinors and a gluon (22 KB per wave with the momenta; no spill left);
+#   per 2^20 events 4.01 -> 3.48 ms (the spinors alone 3.64 ms; a fourth slot leaves LDS for
+#   fewer than two waves per SIMD: 4.11 ms).
+EXT_IN_LDS = {"gg_ttgg": (("EXT_U", "EXT_V"), ("EXT_U", "EXT_V")), "gg_ttg": (("EXT_U", "EXT_V", "EXT_G:1"), ())}
 # read those ahead of the step that uses them (else at each use), and pin the copies
 PREFETCH_EXT = True
 PIN_EXT = True
@@ -268,9 +273,13 @@ class Process:
 
         counted = set()
         # external wavefunctions kept in LDS: slot of each, and the code that computes it
-        ext_lds = () if self.segments else EXT_IN_LDS.get(self.name, ())
+        lds64, lds32 = ((), ()) if self.segments else EXT_IN_LDS.get(self.name, ((), ()))
+        ext_lds = set(lds64) | set(lds32)
         xslot = {}
-        self.xw_init = []
+        self.xw_init = []    # (code, in LDS in the FP64 kernel, in LDS in the FP32 kernel)
+
+        def in_set(key, kinds):
+            return key[0] in kinds or (len(key) > 1 and f"{key[0]}:{key[1]}" in kinds)
 
         def remat(kind):
             if remat_ext is True:
@@ -285,11 +294,11 @@ class Process:
 
         def emit(key):
             kind = key[0]
-            if kind in ext_lds or (len(key) > 1 and f"{kind}:{key[1]}" in ext_lds):
+            if in_set(key, ext_lds):
                 if key not in xslot:
                     code, fl = ext_code(key)
                     xslot[key] = len(self.xw_init)
-                    self.xw_init.append(code)
+                    self.xw_init.append((code, in_set(key, lds64), in_set(key, lds32)))
                     flops[0] += fl
                 return f"XW({xslot[key]})"
             if kind.startswith("EXT") and remat(kind):
@@ -750,14 +759,25 @@ class Process:
         xw_init = getattr(self, "xw_init", [])
         if xw_init:
             nx = len(xw_init)
-            L.append(f"    // {nx} external wavefunctions: in LDS, private to the lane (FP64), or in registers (FP32)")
-            L.append(f"    __shared__ R xw_wg[sizeof(R) == 8 ? WG * {nx} * 8 * 64 : 1];")
-            L.append(f"    R* const xw = xw_wg + (sizeof(R) == 8 ? (threadIdx.x >> 6) * ({nx} * 8 * 64) : 0);")
+            # LDS position of each slot in this precision's kernel, -1: kept in registers
+            pos = {}
+            for j, prec in ((1, "64"), (2, "32")):
+                n, pos[prec] = 0, []
+                for item in xw_init:
+                    pos[prec].append(n if item[j] else -1)
+                    n += 1 if item[j] else 0
+                pos[prec + "n"] = n
+            xwp = ", ".join(f"sizeof(R) == 8 ? {a} : {b}" for a, b in zip(pos["64"], pos["32"]))
+            L.append(f"    // {nx} external wavefunctions computed once: in LDS, private to the lane, or in registers")
+            L.append(f"    constexpr int XWP[{nx}] = {{{xwp}}};")
+            L.append(f"    constexpr int NXL = sizeof(R) == 8 ? {pos['64n']} : {pos['32n']};")
+            L.append("    __shared__ R xw_wg[NXL > 0 ? WG * NXL * 8 * 64 : 1];")
+            L.append("    R* const xw = xw_wg + (threadIdx.x >> 6) * (NXL * 8 * 64);")
             L.append(f"    [[maybe_unused]] W4<R> xwr[{nx}];")
-            for k, code in enumerate(xw_init):
-                L.append(f"    {{ const W4<R> t = {code}; if constexpr (sizeof(R) == 8) st_w4<R>(xw, {k}, lane, t); "
+            for k, (code, _, _) in enumerate(xw_init):
+                L.append(f"    {{ const W4<R> t = {code}; if constexpr (XWP[{k}] >= 0) st_w4<R>(xw, XWP[{k}], lane, t); "
                          f"else xwr[{k}] = t; }}")
-            L.append("#define XW(k) (sizeof(R) == 8 ? ld_w4<R>(xw, k, lane) : xwr[k])")
+            L.append("#define XW(k) (XWP[k] >= 0 ? ld_w4<R>(xw, XWP[k], lane) : xwr[k])")
         L.append(f"    constexpr int NW = {nwin};")
         if jamps_in_lds or mode == "slots":
             acc = "double" if jamp_mode == "atomic64" else "R"

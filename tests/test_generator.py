@@ -130,8 +130,8 @@ def test_every_diagram_evaluated_once(name):
     # from the LDS bases are rebuilt at each use instead; external wavefunctions kept in LDS
     # per lane are computed once at the start (one store each) and read at their uses
     names = re.findall(r"const W4<R> (w\d+) =", src)
-    kept = re.findall(r"st_w4<R>\(xw, (\d+), lane, t\)", src)
-    assert len(kept) == len(set(kept)) == len(P.xw_init) >= len(emit.EXT_IN_LDS.get(name, ()))
+    kept = re.findall(r"if constexpr \(XWP\[(\d+)\] >= 0\) st_w4<R>\(xw, XWP\[\d+\], lane, t\)", src)
+    assert len(kept) == len(set(kept)) == len(P.xw_init) >= len(set().union(*emit.EXT_IN_LDS.get(name, ((), ()))))
     assert all(f"XW({k})" in src for k in kept)
     nodes = P.plan.nodes()
     if name in emit.GLUONS_FROM_LDS:

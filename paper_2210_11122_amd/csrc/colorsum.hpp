@@ -105,6 +105,58 @@ __device__ __forceinline__ double cs1(double jr, double ji, double c00)
     return v;
 }
 
+// Two colour flows (gg -> tt~): D |M_h|^2 = sum over re/im of J^T Chat J with the 2x2 integer
+// matrix, as a scalar in one fixed rounding sequence (rows of Chat J by fused multiply-adds, then
+// the dot product); Chat_rc = aop[r + 16 c], the diagonal tile of the 16x4 table.
+__device__ __forceinline__ double cs2_part(double a, double b, double c00, double c01, double c10, double c11)
+{
+    const double r0 = __builtin_fma(c01, b, c00 * a), r1 = __builtin_fma(c11, b, c10 * a);
+    return __builtin_fma(b, r1, a * r0);
+}
+__device__ __forceinline__ double cs2(double j0r, double j0i, double j1r, double j1i, const double* aop)
+{
+    const double c00 = aop[0], c10 = aop[1], c01 = aop[16], c11 = aop[17];
+    double v = cs2_part(j0r, j1r, c00, c01, c10, c11) + cs2_part(j0i, j1i, c00, c01, c10, c11);
+    asm volatile("" : "+v"(v));
+    return v;
+}
+// Up to 16 flows as a scalar (gg -> tt~g: 6): for re and im, each row of Chat J as a chain of
+// fused multiply-adds over c, then the dot product with J as another; Chat_rc is
+// aop[(c / 4) * 64 + r + 16 (c % 4)], the diagonal 16-block of the table (A = Chat there).
+// j(c, ri) gives the jamps.
+template <int NC, class Jget>
+__device__ __forceinline__ double csn(const Jget& j, const double* aop)
+{
+    static_assert(NC <= 16, "one diagonal tile");
+    double v = 0.0;
+#pragma unroll
+    for (int ri = 0; ri < 2; ++ri) {
+        double s = 0.0;
+#pragma unroll
+        for (int r = 0; r < NC; ++r) {
+            double row = aop[r] * j(0, ri);
+#pragma unroll
+            for (int c = 1; c < NC; ++c) row = __builtin_fma(aop[(c / 4) * 64 + r + 16 * (c % 4)], j(c, ri), row);
+            s = __builtin_fma(j(r, ri), row, s);
+        }
+        v += s;
+    }
+    asm volatile("" : "+v"(v));
+    return v;
+}
+// the scalar forms from a lane's own jamps Jr[2 c + re/im] (amplitude kernels with register jamps)
+template <int NC>
+__device__ __forceinline__ double colour_sum_regs(const double* Jr, const double* __restrict__ aop)
+{
+    static_assert(NC <= 6, "scalar colour sums up to six flows");
+    if constexpr (NC == 1)
+        return cs1(Jr[0], Jr[1], aop[0]);
+    else if constexpr (NC == 2)
+        return cs2(Jr[0], Jr[1], Jr[2], Jr[3], aop);
+    else
+        return csn<NC>([&](int c, int ri) { return Jr[2 * c + ri]; }, aop);
+}
+
 // One (16-event tile, helicity) column block of the FP64 form: returns this lane's share of
 // D * |M_h|^2 for event column i (the four lane groups' shares add up to it).  load(c, ri) gives
 // the jamp of colour c (re/im) of this lane's column.  A: the tile operands in registers when
@@ -115,6 +167,13 @@ __device__ __forceinline__ double cs64_column(const Load& load, const double* A,
     if constexpr (NC == 1) {
         // no tile for a 1x1 matrix: lane group 0 holds the whole value
         return (lane >> 4) == 0 ? cs1((double)load(0, 0), (double)load(0, 1), aop[0]) : 0.0;
+    }
+    if constexpr (NC == 2) {
+        return (lane >> 4) == 0 ? cs2((double)load(0, 0), (double)load(0, 1), (double)load(1, 0), (double)load(1, 1), aop)
+                                : 0.0;
+    }
+    if constexpr (NC > 2 && NC <= 6) {
+        return (lane >> 4) == 0 ? csn<NC>([&](int c, int ri) { return (double)load(c, ri); }, aop) : 0.0;
     }
     constexpr int MT = (NC + 15) / 16, KT = (NC + 3) / 4;
     // the real/imaginary loop stays rolled for the large matrices (register pressure)

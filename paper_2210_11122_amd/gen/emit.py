@@ -840,6 +840,12 @@ class Process:
         if mode == "jamps":
             if fused:
                 L.append("    if (fc.aop) {  // colour sum here: D |M_h|^2 of this lane's event, to [h][event]")
+                L.append("        double me_h;")
+                if not jamps_in_lds and self.nc <= 6:
+                    # up to six flows in FP64: the scalar colour sum from the registers
+                    L.append("        if constexpr (sizeof(R) == 8) {")
+                    L.append("            me_h = colour_sum_regs<NC>(Jr, static_cast<const double*>(fc.aop));")
+                    L.append("        } else {")
                 if jamps_in_lds:
                     src = "Jl"
                     L.append("        __syncthreads();  // every jamp update of the wave has completed")
@@ -859,7 +865,6 @@ class Process:
                     L.append("#pragma unroll")
                     L.append("        for (int s = 0; s < 2 * NC; ++s) Js[s * 64 + lane] = Jr[s];")
                     L.append("        __syncthreads();")
-                L.append("        double me_h;")
                 L.append("        if constexpr (sizeof(R) == 8)")
                 L.append(f"            me_h = colour_sum_lds<NC>({src}, static_cast<const double*>(fc.aop), lane);")
                 L.append("        else if (fc.form == ME_MIXED_BF16)")
@@ -868,6 +873,8 @@ class Process:
                 L.append("        else")
                 L.append(f"            me_h = colour_sum_lds_h16<NC, Fp16Terms>({src}, static_cast<const _Float16*>(fc.aop), "
                          "static_cast<const _Float16*>(fc.aop), 0, lane);")
+                if not jamps_in_lds and self.nc <= 6:
+                    L.append("        }")
                 if hsum:
                     L.append("        if constexpr (hsum) {  // the helicity sum: the separate kernel's groups and order")
                     L.append("            __shared__ double red[16 * 64];")

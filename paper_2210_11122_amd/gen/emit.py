@@ -45,8 +45,11 @@ PIN_MOMENTA = True
 # (the second __launch_bounds__ argument: it caps the registers per lane at 512 / waves)
 MIN_WAVES = {"gg_tt": (4, 5), "gg_ttg": (2, 3), "gg_ttgg": (1, 2), "gg_ttggg": (1, 2)}
 # name -> waves per workgroup (FP64, FP32 kernels): consecutive helicities of one 64-event block
-# that share the staged momenta (less LDS per wave where LDS, not registers, limits the waves)
-WAVES_PER_GROUP = {"gg_ttgg": (4, 4), "gg_ttggg": (4, 8)}
+# that share the staged momenta (less LDS per wave where LDS, not registers, limits the waves).
+# The FP32 kernels with register jamps stage them in the momentum area for the colour sum and
+# keep one wave per group.  gg_tt FP64 per 2^19 events 0.197 -> 0.182 ms; gg_ttg FP64 per 2^20
+# 3.14 -> 2.77 ms (its three LDS externals and shared momenta then fit two waves per SIMD)
+WAVES_PER_GROUP = {"gg_tt": (4, 1), "gg_ttg": (4, 1), "gg_ttgg": (4, 4), "gg_ttggg": (4, 8)}
 # processes whose programs keep no external gluon wavefunction in registers: the workgroup
 # stages each event's gluon bases in LDS once (helas.hpp, stage_gluon_basis) and every use
 # rebuilds the polarisation vector from there.  It removes the FP64 kernels' spills but costs
@@ -64,9 +67,10 @@ GLUONS_FROM_LDS = set()
 #   measured 24.8 ms).
 # * gg_ttgg FP32: the same two, 2 KB per wave each, with four waves per workgroup (78 KB, two per
 #   CU); per 2^19 events 14.54 -> 14.20 ms (four waves alone: 14.33 ms; one spinor: 14.45 ms).
-# * gg_ttg FP64: the top spinors and a gluon (22 KB per wave with the momenta; no spill left);
-#   per 2^20 events 4.01 -> 3.48 ms (the spinors alone 3.64 ms; a fourth slot leaves LDS for
-#   fewer than two waves per SIMD: 4.11 ms).
+# * gg_ttg FP64: the top spinors and a gluon (no spill left); per 2^20 events 4.01 -> 3.48 ms
+#   with one wave per workgroup (the spinors alone 3.64 ms; a fourth slot, 4.11 ms, left LDS
+#   for fewer than two waves per SIMD; with four waves per group a fourth slot gives 2.94 ms
+#   against 2.77 ms for three).
 EXT_IN_LDS = {"gg_ttgg": (("EXT_U", "EXT_V"), ("EXT_U", "EXT_V")), "gg_ttg": (("EXT_U", "EXT_V", "EXT_G:1"), ())}
 # read those ahead of the step that uses them (else at each use), and pin the copies
 PREFETCH_EXT = True
@@ -708,8 +712,9 @@ class Process:
         L.append("template <class R, bool SDE, bool HS = false>" if hsum else "template <class R, bool SDE>")
         w64, w32 = MIN_WAVES.get(self.name, (1, 1))
         g64, g32 = WAVES_PER_GROUP.get(self.name, (1, 1))
-        if (g64, g32) != (1, 1) and not (jamps_in_lds or mode == "slots"):
-            # register jamps are staged in the (shared) momentum area for the colour sum
+        if (g32 != 1 or (g64 != 1 and self.nc > 6)) and not (jamps_in_lds or mode == "slots"):
+            # register jamps are staged in the (shared) momentum area for the colour sum, except
+            # in the FP64 kernels with up to six flows, whose colour sum stays in registers
             raise ValueError("several waves per workgroup need per-wave LDS jamps")
         if hsum and (g64, g32) != (1, 1):
             raise ValueError("the helicity sum in the kernel sizes the workgroup by the good helicities")

@@ -43,13 +43,15 @@ PREFETCH_MOMENTA = True
 PIN_MOMENTA = True
 # name -> minimum waves per SIMD asked of the compiler for the (FP64, FP32) amplitude kernels
 # (the second __launch_bounds__ argument: it caps the registers per lane at 512 / waves)
-MIN_WAVES = {"gg_tt": (4, 5), "gg_ttg": (2, 3), "gg_ttgg": (1, 2), "gg_ttggg": (1, 2)}
+MIN_WAVES = {"gg_tt": (4, 6), "gg_ttg": (2, 3), "gg_ttgg": (1, 2), "gg_ttggg": (1, 2)}
 # name -> waves per workgroup (FP64, FP32 kernels): consecutive helicities of one 64-event block
 # that share the staged momenta (less LDS per wave where LDS, not registers, limits the waves).
-# The FP32 kernels with register jamps stage them in the momentum area for the colour sum and
-# keep one wave per group.  gg_tt FP64 per 2^19 events 0.197 -> 0.182 ms; gg_ttg FP64 per 2^20
-# 3.14 -> 2.77 ms (its three LDS externals and shared momenta then fit two waves per SIMD)
-WAVES_PER_GROUP = {"gg_tt": (4, 1), "gg_ttg": (4, 1), "gg_ttgg": (4, 4), "gg_ttggg": (4, 8)}
+# With several waves per group, FP32 kernels with register jamps stage them for the colour sum in
+# an LDS area of their own (a single wave reuses the momentum area).  gg_tt FP64 per 2^19 events
+# 0.197 -> 0.182 ms, mixed (six waves per SIMD) 0.272 -> 0.252 ms; gg_ttg FP64 per 2^20 3.14 ->
+# 2.77 ms (its three LDS externals and shared momenta then fit two waves per SIMD), mixed 2.86 ->
+# 2.62 ms (2.59 ms with its top spinors in LDS as well)
+WAVES_PER_GROUP = {"gg_tt": (4, 4), "gg_ttg": (4, 4), "gg_ttgg": (4, 4), "gg_ttggg": (4, 8)}
 # processes whose programs keep no external gluon wavefunction in registers: the workgroup
 # stages each event's gluon bases in LDS once (helas.hpp, stage_gluon_basis) and every use
 # rebuilds the polarisation vector from there.  It removes the FP64 kernels' spills but costs
@@ -71,7 +73,8 @@ GLUONS_FROM_LDS = set()
 #   with one wave per workgroup (the spinors alone 3.64 ms; a fourth slot, 4.11 ms, left LDS
 #   for fewer than two waves per SIMD; with four waves per group a fourth slot gives 2.94 ms
 #   against 2.77 ms for three).
-EXT_IN_LDS = {"gg_ttgg": (("EXT_U", "EXT_V"), ("EXT_U", "EXT_V")), "gg_ttg": (("EXT_U", "EXT_V", "EXT_G:1"), ())}
+EXT_IN_LDS = {"gg_ttgg": (("EXT_U", "EXT_V"), ("EXT_U", "EXT_V")),
+              "gg_ttg": (("EXT_U", "EXT_V", "EXT_G:1"), ("EXT_U", "EXT_V"))}
 # read those ahead of the step that uses them (else at each use), and pin the copies
 PREFETCH_EXT = True
 PIN_EXT = True
@@ -712,10 +715,6 @@ class Process:
         L.append("template <class R, bool SDE, bool HS = false>" if hsum else "template <class R, bool SDE>")
         w64, w32 = MIN_WAVES.get(self.name, (1, 1))
         g64, g32 = WAVES_PER_GROUP.get(self.name, (1, 1))
-        if (g32 != 1 or (g64 != 1 and self.nc > 6)) and not (jamps_in_lds or mode == "slots"):
-            # register jamps are staged in the (shared) momentum area for the colour sum, except
-            # in the FP64 kernels with up to six flows, whose colour sum stays in registers
-            raise ValueError("several waves per workgroup need per-wave LDS jamps")
         if hsum and (g64, g32) != (1, 1):
             raise ValueError("the helicity sum in the kernel sizes the workgroup by the good helicities")
         threads = "64" if (g64, g32) == (1, 1) else f"64 * (sizeof(R) == 8 ? {g64} : {g32})"
@@ -867,6 +866,10 @@ class Process:
                         L.append("        }")
                     else:
                         L.append("        R* Js = reinterpret_cast<R*>(lds);")
+                        L.append("        if constexpr (WG > 1) {  // the momentum area is shared: a staging area per wave")
+                        L.append("            __shared__ R Jst_wg[WG * 2 * NC * 64];")
+                        L.append("            Js = Jst_wg + (threadIdx.x >> 6) * (2 * NC * 64);")
+                        L.append("        }")
                     L.append("#pragma unroll")
                     L.append("        for (int s = 0; s < 2 * NC; ++s) Js[s * 64 + lane] = Jr[s];")
                     L.append("        __syncthreads();")

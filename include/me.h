@@ -5,8 +5,9 @@
  * over the initial states (the per-event ME calculation of the paper, Sec. 1 and 2; the
  * process set ee->mumu, gg->tt~ + 0..3 gluons of Sec. 2).  The GPU path evaluates every
  * Feynman diagram with HELAS-style wavefunctions, accumulates the colour-flow amplitudes,
- * contracts them with the colour matrix on the matrix cores and sums the helicities that
- * a pre-pass found to contribute.
+ * contracts them with the colour matrix (on the matrix cores; in FP64 with up to six flows,
+ * as scalar fused multiply-adds in each lane) and sums the helicities that a pre-pass found
+ * to contribute.
  *
  * Conventions.  Units GeV; momenta (E, px, py, pz), metric (+,-,-,-).  Particle order:
  *   ee_mumu  (e+, e-, mu+, mu-)
@@ -214,11 +215,11 @@ int me_profile(me_handle *h, int enable, double *ms_amp, double *ms_colour, int6
  * ME_OPT_FUSED_COLOUR (default 1): for the plain |M|^2 (me_sigma, me_sigma_alphas) of a
  * process whose amplitude kernel ends holding all jamps of its lanes (every process but
  * gg_ttggg, whose jamps come out of a window of partial sums), in every precision, the
- * kernel contracts them with the colour matrix itself (the same matrix-core tiles, operand
- * splits, sums and order as the separate colour-sum kernel of that precision, so each
- * helicity's |M_h|^2 is bitwise the same) and writes one FP64 value per (event, helicity)
- * instead of the jamps; a second kernel sums the helicities in the separate kernel's groups
- * and order.  0: always the separate colour-sum kernel.  Both settings, and the calls that
+ * kernel contracts them with the colour matrix itself (the same matrix-core tiles, or scalar
+ * forms, operand splits, sums and order as the separate colour-sum kernel of that precision,
+ * so each helicity's |M_h|^2 is bitwise the same) and writes one FP64 value per (event,
+ * helicity) instead of the jamps; a second kernel sums the helicities in the separate
+ * kernel's groups and order (the e+e- processes sum them in the same kernel).  0: always the separate colour-sum kernel.  Both settings, and the calls that
  * need the jamps (me_sigma_hel, me_sigma_select), give bitwise the same |M|^2.
  * ME_EINVAL for an unknown option or a value other than 0 or 1. */
 enum { ME_OPT_FUSED_COLOUR = 1 };

@@ -129,6 +129,18 @@ def sweep(processes, precisions, log2_sizes, torch, min_ms=300.0):
     return out
 
 
+def sweep_markdown(res):
+    """the sweep as a table: MEs/s per process and form (rows) and batch size (columns)"""
+    sizes = sorted({r["n_evt"] for rows in res.values() for r in rows})
+    L = ["| process | form | " + " | ".join(f"2^{n.bit_length() - 1}" for n in sizes) + " |",
+         "|---|---|" + "---|" * len(sizes)]
+    for name, rows in res.items():
+        for prec in dict.fromkeys(r["precision"] for r in rows):
+            by = {r["n_evt"]: r["MEs_per_s"] for r in rows if r["precision"] == prec}
+            L.append(f"| {name} | {prec} | " + " | ".join(f"{by[n]:.3g}" if n in by else "-" for n in sizes) + " |")
+    return "\n".join(L) + "\n"
+
+
 def cpu_baseline(name, n_evt_total, params, budget_s, threads):
     """the oracle as it stands on a bounded sample: first events of the same RAMBO stream"""
     import numpy as np
@@ -291,6 +303,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--sweep", action="store_true",
                     help="batch-size sweep 2^8..2^20 of every process instead of the benchmark line")
+    ap.add_argument("--sweep-md", default=None, metavar="MD_PATH", help="with --sweep: also write it as markdown")
     ap.add_argument("--table", default=None, metavar="MD_PATH",
                     help="per-process table (FP64 and mixed MEs/s, roofline fractions, mixed errors, oracle "
                          "MEs/s) as one JSON line, and as markdown to MD_PATH, instead of the benchmark line")
@@ -318,6 +331,9 @@ def main():
     if args.sweep:
         sizes = lambda nm: range(8, (19 if nm == "gg_ttggg" else 21), 2)
         res = sweep(["ee_mumu", "gg_tt", "gg_ttg", "gg_ttgg", "gg_ttggg"], ["fp64", "mixed_fp16"], sizes, torch)
+        if args.sweep_md:
+            with open(args.sweep_md, "w") as fh:
+                fh.write(sweep_markdown(res))
         print(json.dumps({"metric": "batch-size sweep: matrix elements/sec at 1 GPU", "unit": "MEs/s",
                           "data": "synthetic (RAMBO phase space on device, seed 0)", "sweep": res}), flush=True)
         return

@@ -129,6 +129,12 @@ def sweep(processes, precisions, log2_sizes, torch, min_ms=300.0):
     return out
 
 
+def roofline_bound(bytes_per_me, flops_per_me):
+    """'hbm' if moving an ME's bytes at the HBM peak takes longer than its algorithmic flops at
+    the FP64 peak (fewer flops per byte than the machine balance), else 'alu'"""
+    return "hbm" if bytes_per_me / (HBM_PEAK_GBS * 1e9) > flops_per_me / (FP64_VALU_PEAK_TFLOPS * 1e12) else "alu"
+
+
 def sweep_markdown(res):
     """the sweep as a table: MEs/s per process and form (rows) and batch size (columns)"""
     sizes = sorted({r["n_evt"] for rows in res.values() for r in rows})
@@ -420,7 +426,7 @@ def main():
                      "per_call_GBs": mes64 * bytes_me / 1e9, "per_call_frac": mes64 * bytes_me / (HBM_PEAK_GBS * 1e9),
                      "amp_kernel_GBs": hbm_launch, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     flops_me = info["n_good_hel"] * (info["flops_amp_lane"] + info["flops_colour_lane"])
-    if bytes_me / (HBM_PEAK_GBS * 1e9) > flops_me / (FP64_VALU_PEAK_TFLOPS * 1e12):
+    if roofline_bound(bytes_me, flops_me) == "hbm":
         # fewer flops per byte than the machine balance (ee_mumu): HBM sets the roofline
         rf = result["roofline"]
         rf.update({"bound": "hbm", "kernel": rf["kernel"] + "; algorithmic bytes: momenta in, |M|^2 out",

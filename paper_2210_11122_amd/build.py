@@ -28,16 +28,8 @@ def generate(names=None):
     return emit.generate(GEN, names or SUPPORTED)
 
 
-# The segment kernels of the largest process spill registers.  With this compiler, their
-# VGPR-to-AGPR spill code gave wrong jamps (checked against the CPU oracle flow by flow,
-# while the same program with extra debug stores, or with AGPR spilling disabled, was
-# right); spills of these kernels therefore go to scratch memory.
-SEGMENT_FLAGS = ["-mllvm", "-amdgpu-spill-vgpr-to-agpr=0"]
-
-
 def _compile(src, obj, log):
-    extra = SEGMENT_FLAGS if "_amp_seg" in os.path.basename(src) else []
-    cmd = [HIPCC] + FLAGS + extra + ["-x", "hip", "-c", src, "-o", obj]
+    cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr[-4000:]}")

@@ -51,7 +51,9 @@ MIN_WAVES = {"gg_tt": (4, 6), "gg_ttg": (2, 3), "gg_ttgg": (1, 2), "gg_ttggg": (
 # 0.197 -> 0.182 ms, mixed (six waves per SIMD) 0.272 -> 0.252 ms; gg_ttg FP64 per 2^20 3.14 ->
 # 2.77 ms (its three LDS externals and shared momenta then fit two waves per SIMD), mixed 2.86 ->
 # 2.62 ms (2.59 ms with its top spinors in LDS as well)
-WAVES_PER_GROUP = {"gg_tt": (4, 4), "gg_ttg": (4, 4), "gg_ttgg": (4, 4), "gg_ttggg": (4, 8)}
+# The test process gg_gg has six good helicities, so its second group of four carries two spare
+# waves: its parity tests cover that path.
+WAVES_PER_GROUP = {"gg_tt": (4, 4), "gg_ttg": (4, 4), "gg_ttgg": (4, 4), "gg_ttggg": (4, 8), "gg_gg": (4, 4)}
 # processes whose programs keep no external gluon wavefunction in registers: the workgroup
 # stages each event's gluon bases in LDS once (helas.hpp, stage_gluon_basis) and every use
 # rebuilds the polarisation vector from there.  It removes the FP64 kernels' spills but costs

@@ -92,6 +92,39 @@ def test_per_helicity_matches_oracle(name):
             assert abs(hel[e, k] - ref[hh]) <= 1e-12 * scale
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed_fp16", "mixed_bf16"])
+def test_spare_waves_of_a_partial_group(precision):
+    """gg_gg has six good helicities and runs four helicity waves per workgroup, so the second
+    group of every event block holds two spare waves, which repeat a helicity and write nothing.
+    Its |M|^2 (colour sum in the amplitude kernel) and its per-helicity output (jamps through
+    the separate colour sum) against the oracle, on a ragged batch"""
+    name, n = "gg_gg", 1000
+    print(f"case spare waves {name} {precision}", flush=True)
+    proc = make_process(name, precision)
+    n_good = proc.info["n_good_hel"]
+    assert n_good % 4 != 0
+    p = oracle.rambo(21, W.sqrt_s(name), W.final_masses(name), n)
+    x = torch.from_numpy(p).cuda()
+    plain = proc.sigma(x).cpu().numpy()
+    tot, hel = proc.sigma(x, per_helicity=True)
+    tot, hel = tot.cpu().numpy(), hel.cpu().numpy()
+    assert np.array_equal(plain, tot)
+    # the per-helicity values are colour-summed, not averaged
+    assert np.allclose(hel.sum(axis=1) / proc.info["avg_factor"], tot, rtol=1e-13, atol=0)
+    if precision == "fp64":
+        check_fp64(name, p, plain)
+        good = proc.good_helicities()
+        npar = W.n_par(name)
+        for e in range(0, n, 97):
+            _, ref = oracle.me(name, p[e], params=W.PARAMS, per_helicity=True)
+            for k, lam in enumerate(good):
+                hh = sum(((l + 1) // 2) << (npar - 1 - i) for i, l in enumerate(lam))
+                assert abs(hel[e, k] - ref[hh]) <= 1e-12 * ref.max()
+    else:
+        rel = np.abs(plain / oracle.me_batch(name, p, params=W.PARAMS) - 1)
+        assert rel.max() < 1e-4
+
+
 def test_ee_mumu_helicity_filter_keeps_four():
     proc = make_process("ee_mumu")
     good = proc.good_helicities()

@@ -1,5 +1,5 @@
-"""Host logic of bench.py that needs no GPU: which roofline a process is measured against and
-the sweep's markdown table."""
+"""Host logic of bench.py that needs no GPU: which roofline a process is measured against, the
+sweep's markdown table, and the refusal of more than one GPU."""
 import bench
 
 
@@ -20,3 +20,16 @@ def test_sweep_markdown_table():
     assert lines[0] == "| process | form | 2^8 | 2^10 |"
     assert lines[2] == "| gg_tt | fp64 | 1e+08 | 2e+08 |"
     assert lines[3] == "| gg_tt | mixed_fp16 | 1.5e+08 | - |"
+
+
+def test_more_than_one_gpu_is_refused():
+    """the measurement covers one GPU; asked for more, bench.py says so and exits with status 2
+    before touching a device"""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=root)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""

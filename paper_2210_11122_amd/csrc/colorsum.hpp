@@ -105,6 +105,36 @@ __device__ __forceinline__ double cs1(double jr, double ji, double c00)
     return v;
 }
 
+// One colour flow in a mixed form, as the 16-bit tile computes it for that column: the jamp
+// scaled by a power of two into [1/2, 1), split into hi + lo * 2^-p, both multiplied by the one
+// operand (exact in FP32, the only non-zero products the tile adds), and the dot product formed
+// in FP64 and unscaled.  Bitwise the tile's value (16-bit element types below).
+template <class T>
+__device__ __forceinline__ double cs1_h16_part(float x, float a00)
+{
+    float mx = fabsf(x);
+    int ex = 0;
+    if (mx > 0.0f) frexpf(mx, &ex);
+    const float s = ldexpf(1.0f, -ex);
+    const float v = x * s;
+    const typename T::elem hi = T::round(v);
+    const typename T::elem lo = T::round((v - T::value(hi)) * T::LO);
+    const float dh = a00 * T::value(hi), dl = a00 * T::value(lo);
+    double acc = 0.0;
+    acc += (double)v * ((double)dh + (double)dl * (1.0 / T::LO));
+    return acc / ((double)s * (double)s);
+}
+template <class T>
+__device__ __forceinline__ double cs1_h16(float jr, float ji, const typename T::elem* aop)
+{
+    const float a00 = T::value(aop[0]);
+    double part = 0.0;
+    part += cs1_h16_part<T>(jr, a00);
+    part += cs1_h16_part<T>(ji, a00);
+    asm volatile("" : "+v"(part));
+    return part;
+}
+
 // Two colour flows (gg -> tt~): D |M_h|^2 = sum over re/im of J^T Chat J with the 2x2 integer
 // matrix, as a scalar in one fixed rounding sequence (rows of Chat J by fused multiply-adds, then
 // the dot product); Chat_rc = aop[r + 16 c], the diagonal tile of the 16x4 table.

@@ -87,13 +87,13 @@ PIN_EXT = True
 # call; gg_tt at 2^19 was slower (2.36e9 -> 2.20e9 MEs/s FP64, 1.98e9 -> 1.68e9 mixed), its
 # 16-wave workgroups waiting for each other at the barriers
 HEL_SUM_IN_KERNEL = {"ee_mumu", "ee_mumu_z"}
-# ... and whose FP64 |M|^2 comes from a kernel with one lane per event that evaluates the
-# event's good helicities in turn (amp_lanes): no helicity waves to combine, no barrier after
-# the momentum staging; the mixed forms keep the helicity-wave kernel (their colour sum is the
-# FP16 / BF16 matrix-core form, which works on 16-event tiles)
+# ... and whose |M|^2 comes from a kernel with one lane per event that evaluates the event's
+# good helicities in turn (amp_lanes): no helicity waves to combine, no barrier after the
+# momentum staging.  In the mixed forms the one-flow 16-bit tile has a scalar equivalent
+# (colorsum.hpp, cs1_h16), so they use it too
 LANE_PER_EVENT = {"ee_mumu", "ee_mumu_z"}
-# the batch size from which the FP64 calls take that kernel (smaller batches fill the GPU only
-# with a wave per helicity)
+# the batch size from which calls take that kernel (smaller batches fill the GPU only with a
+# wave per helicity)
 LANE_MIN_EVENTS = 1 << 16
 ALL_PROCESSES = ["ee_mumu", "gg_tt", "gg_ttg", "gg_ttgg", "gg_ttggg", "gg_gg", "ee_mumu_z"]
 # electroweak constants of ee -> mumu with Z exchange: M_Z, Gamma_Z, M_W [GeV]
@@ -659,9 +659,10 @@ class Process:
                 if fused and self.name in HEL_SUM_IN_KERNEL:
                     L.append("    if (fc && fc->hsum_out) {  // the kernel also sums the helicities")
                     if nm in LANE_PER_EVENT:
-                        L.append("        // FP64 batches large enough to fill the GPU with one lane per event")
-                        L.append(f"        if (sizeof(R) == 8 && n_evt >= {LANE_MIN_EVENTS}) {{")
-                        L.append("            hipLaunchKernelGGL(amp_lanes, dim3((unsigned)((n_evt + 63) / 64)), dim3(64), 0, st, "
+                        L.append("        // batches large enough to fill the GPU with one lane per event (the mixed forms when")
+                        L.append("        // their one colour operand is exact in the 16-bit type, as the scalar form assumes)")
+                        L.append(f"        if (n_evt >= {LANE_MIN_EVENTS} && (sizeof(R) == 8 || !(fc->lo_mask & 1))) {{")
+                        L.append("            hipLaunchKernelGGL((amp_lanes<R>), dim3((unsigned)((n_evt + 63) / 64)), dim3(64), 0, st, "
                                  "mom, n_evt, hel, n_good, gs, *fc);")
                         L.append("            return hipGetLastError();")
                         L.append("        }")
@@ -923,17 +924,17 @@ class Process:
         return L
 
     def _lane_kernel_text(self, body):
-        """FP64 kernel of the e+e- processes with one lane per event: the momenta staged once,
-        then for each good helicity the diagram program, the colour sum (one flow) and the
-        helicity sum in the groups and order of the separate helicity-sum kernel, so the result
-        is bitwise that of the other paths."""
+        """Kernel of the e+e- processes with one lane per event: the momenta staged once, then
+        for each good helicity the diagram program, the colour sum (one flow; in the mixed forms
+        the scalar equivalent of the 16-bit tile) and the helicity sum in the groups and order of
+        the separate helicity-sum kernel, so the result is bitwise that of the other paths."""
         if self.nc != 1:
             raise ValueError("the lane-per-event kernel handles one colour flow")
         L = []
+        L.append("template <class R>")
         L.append("__global__ __launch_bounds__(64, 4) void amp_lanes(const double* __restrict__ mom, int64_t n_evt, "
                  "const signed char* __restrict__ hel, int n_good, double gs, FusedColour fc)")
         L.append("{")
-        L.append("    typedef double R;")
         L.append("    __shared__ double lds[4 * NPAR * 64];")
         L.append("    const int lane = threadIdx.x;")
         L.append("    const int64_t e0 = xcd_remap(blockIdx.x, gridDim.x) * 64;")
@@ -944,7 +945,6 @@ class Process:
         L.append("#define PM(i) lds_p4(lds, i, lane)")
         L.append("#define SDEACC(d, k) do { } while (0)")
         L.append("#define JADD(s, ri, v) (Jr[2 * (s) + (ri)] += (v))")
-        L.append("    const double c00 = static_cast<const double*>(fc.aop)[0];")
         L.append("    double s = 0.0, m = 0.0;")
         L.append("    int in_group = 0;")
         L.append("#pragma unroll 1")
@@ -956,7 +956,12 @@ class Process:
         L.append("        cx<R> a;")
         L += ["    " + ln for ln in body]
         L.append("        asm volatile(\"\" : \"+v\"(Jr[0]), \"+v\"(Jr[1]));  // the jamp as the other paths store it")
-        L.append("        m += cs1(Jr[0], Jr[1], c00);")
+        L.append("        if constexpr (sizeof(R) == 8)")
+        L.append("            m += cs1(Jr[0], Jr[1], static_cast<const double*>(fc.aop)[0]);")
+        L.append("        else if (fc.form == ME_MIXED_BF16)")
+        L.append("            m += cs1_h16<Bf16Terms>(Jr[0], Jr[1], static_cast<const __bf16*>(fc.aop));")
+        L.append("        else")
+        L.append("            m += cs1_h16<Fp16Terms>(Jr[0], Jr[1], static_cast<const _Float16*>(fc.aop));")
         L.append("        if (++in_group == fc.hel_per_group || h + 1 == n_good) {")
         L.append("            s += m;")
         L.append("            m = 0.0;")

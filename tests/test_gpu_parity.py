@@ -270,17 +270,19 @@ def test_fused_colour_sum_equals_separate_kernel(name, precision):
     assert L.me_set_option(proc._h, binding.ME_OPT_FUSED_COLOUR, 2) == -1
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed_fp16", "mixed_bf16"])
 @pytest.mark.parametrize("name", ["ee_mumu", "ee_mumu_z"])
-def test_lane_per_event_kernel(name):
-    """FP64 e+e- batches of 2^16 events or more take the kernel with one lane per event (all
-    good helicities in turn); its results are bitwise those of the helicity-wave kernel (the
-    same events in batches below 2^16) and of the separate colour-sum path, and the oracle's
-    within the FP64 bar (every event, ragged tail)"""
+def test_lane_per_event_kernel(name, precision):
+    """e+e- batches of 2^16 events or more take the kernel with one lane per event (all good
+    helicities in turn; in the mixed forms the scalar equivalent of the one-flow 16-bit tile);
+    its results are bitwise those of the helicity-wave kernel (the same events in batches below
+    2^16) and of the separate colour-sum path, and the oracle's within the FP64 bar, or the
+    mixed forms' (every event, ragged tail)"""
     n = (1 << 16) + 4099
-    print(f"case lane per event {name} n={n}", flush=True)
+    print(f"case lane per event {name} {precision} n={n}", flush=True)
     p = oracle.rambo(17, W.sqrt_s(name), W.final_masses(name), n)
     x = torch.from_numpy(p).cuda()
-    proc = make_process(name)
+    proc = make_process(name, precision)
     lanes = proc.sigma(x).cpu().numpy()
     cut = 40000
     waves = np.concatenate([proc.sigma(x[:cut].contiguous()).cpu().numpy(),
@@ -288,7 +290,10 @@ def test_lane_per_event_kernel(name):
     assert np.array_equal(lanes, waves)
     proc.set_fused_colour(False)
     assert np.array_equal(lanes, proc.sigma(x).cpu().numpy())
-    check_fp64(name, p, lanes)
+    if precision == "fp64":
+        check_fp64(name, p, lanes)
+    else:
+        assert np.max(np.abs(lanes / oracle.me_batch(name, p, params=W.PARAMS) - 1)) < 1e-4
 
 
 def test_large_batch_sampled_parity():

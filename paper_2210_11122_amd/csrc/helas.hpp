@@ -97,6 +97,22 @@ __device__ __forceinline__ cx<R> dot(const W4<R>& a, const W4<R>& b)
 {
     return cfms(a.c[3], b.c[3], cfms(a.c[2], b.c[2], cfms(a.c[1], b.c[1], a.c[0] * b.c[0])));
 }
+// x + u y for a unit u = UR + i UI of the Gaussian integers (1, -1, i or -i): the vertices are
+// linear in each wavefunction, so amplitudes that differ in one operand only sum before the vertex
+template <class R, int UR, int UI>
+__device__ __forceinline__ W4<R> w4_acc(const W4<R>& x, const W4<R>& y)
+{
+    static_assert(UR * UR + UI * UI == 1, "a unit of the Gaussian integers");
+    W4<R> o;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        if (UR == 1) o.c[mu] = x.c[mu] + y.c[mu];
+        else if (UR == -1) o.c[mu] = x.c[mu] - y.c[mu];
+        else if (UI == 1) o.c[mu] = x.c[mu] + mul_i(y.c[mu]);
+        else o.c[mu] = x.c[mu] - mul_i(y.c[mu]);
+    }
+    return o;
+}
 // real vector in the working precision
 template <class R>
 struct R4 {

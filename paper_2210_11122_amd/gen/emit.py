@@ -34,6 +34,10 @@ SEGMENTS = {"gg_ttggg": (14, 35, 2.0)}
 SEGMENT_CUT = "amps"
 # sum the amplitudes of entries with proportional colour coefficients before their jamp updates
 PRESUM = True
+# within such a class, evaluate the entries that differ in one wavefunction only (same vertex,
+# the other operands and every momentum the same) as one vertex on the sum of those
+# wavefunctions, each times its unit factor: the vertices are linear in each wavefunction
+LINEAR_MERGE = True
 # sa += u a for the units u of the Gaussian integers
 ACC_TEXT = {(1, 0): "sa.r += a.r; sa.i += a.i;", (-1, 0): "sa.r -= a.r; sa.i -= a.i;",
             (0, 1): "sa.r -= a.i; sa.i += a.r;", (0, -1): "sa.r += a.i; sa.i -= a.r;"}
@@ -365,52 +369,81 @@ class Process:
             order = D.schedule(self.plan, remat_ext=remat_ext, amps=self.units())
         # the amplitude entries in the order their `a = amp_...` lines are emitted
         self.emit_order = [m[0] for unit in order for m in self.unit_members(unit)]
+        # per `a = amp_...` line: [(entry, unit factor relative to the line's first entry)]
+        self.emit_groups = []
+
+        def call_of(member):
+            """emit the nodes of one amplitude entry; its vertex call as (function, arguments)"""
+            di, (kind, j), deps, _ = member
+            if kind == "FFV":
+                return "amp_ffv<R>", [emit(k) for k in deps] + ["gs"]
+            t = self.diagrams[di][j]
+            kids = D.children(t)
+            wx = emit(deps[0])
+            ws = [emit(k) for k in deps[1:]]
+            if t[0] == "V3":
+                kx = K((self.ng - 1,)) if self.kind == "gluon" else "(-" + K(D.leaves(t)) + ")"
+                ka, kb = K(D.leaves(kids[0])), K(D.leaves(kids[1]))
+                return "amp_vvv<R>", [wx, kx, ws[0], ka, ws[1], kb, "gs"]
+            return f"amp_vvvv<R, {t[1]}>", [wx, ws[0], ws[1], ws[2], "gs"]
+
+        def amp_flops(fn):
+            return FLOPS["amp_ffv" if fn.startswith("amp_ffv") else "amp_vvv" if fn.startswith("amp_vvv<")
+                         else "amp_vvvv"]
+
         for ai, unit in enumerate(order):
             members = self.unit_members(unit)
-            for mi, (di, opt, deps, (ur, ui)) in enumerate(members):
-                last = mi == len(members) - 1
-                d = self.diagrams[di]
-                kind, j = opt
+            groups = self._linear_groups(members) if LINEAR_MERGE else [[i] for i in range(len(members))]
+            for gi, grp in enumerate(groups):
+                last = gi == len(groups) - 1
                 m_node = len(out)
-                if kind == "FFV":
-                    wu, wv, wg = (emit(k) for k in deps)
-                    m_amp = len(out)
-                    out.append(f"    a = amp_ffv<R>({wu}, {wv}, {wg}, gs);")
-                    flops[0] += FLOPS["amp_ffv"]
-                else:
-                    t = d[j]
-                    kids = D.children(t)
-                    wx = emit(deps[0])
-                    ws = [emit(k) for k in deps[1:]]
-                    m_amp = len(out)
-                    if self.kind == "gluon":
-                        kx = K((self.ng - 1,))
-                    else:
-                        kx = "(-" + K(D.leaves(t)) + ")"
-                    if t[0] == "V3":
-                        ka, kb = K(D.leaves(kids[0])), K(D.leaves(kids[1]))
-                        out.append(f"    a = amp_vvv<R>({wx}, {kx}, {ws[0]}, {ka}, {ws[1]}, {kb}, gs);")
-                        flops[0] += FLOPS["amp_vvv"]
-                    else:
-                        out.append(f"    a = amp_vvvv<R, {t[1]}>({wx}, {ws[0]}, {ws[1]}, {ws[2]}, gs);")
-                        flops[0] += FLOPS["amp_vvvv"]
+                calls = [call_of(members[i]) for i in grp]
+                m_amp = len(out)
+                fn, args = calls[0]
+                uf = members[grp[0]][3]
+                line = [(members[grp[0]][0], (1, 0))]
+                if len(grp) > 1:
+                    # one vertex on the sum of the operands that differ, each times its unit
+                    # relative to the first member's: sum_m u_m V(.., w_m, ..) = u_f V(.., sum_m (u_m/u_f) w_m, ..)
+                    diff = {k for f, a in calls[1:] for k in range(len(args)) if a[k] != args[k]}
+                    assert len(diff) == 1 and all(f == fn for f, _ in calls), (unit[0], grp)
+                    k = diff.pop()
+                    comb = args[k]
+                    for i, (_, a) in zip(grp[1:], calls[1:]):
+                        ur, ui = members[i][3]
+                        rel = (ur * uf[0] + ui * uf[1], ui * uf[0] - ur * uf[1])
+                        comb = f"w4_acc<R, {rel[0]}, {rel[1]}>({comb}, {a[k]})"
+                        flops[0] += 8
+                        line.append((members[i][0], rel))
+                    args = args[:k] + [comb] + args[k + 1:]
+                self.emit_groups.append(line)
+                out.append(f"    a = {fn}({', '.join(args)});")
+                flops[0] += amp_flops(fn)
                 out.append("    pin_cx<R>(a);")
                 if self.fd_index is not None:
-                    out.append(f"    SDEACC({self.fd_index[di]}, {self.kweight[di]!r});")
-                # amplitudes of a class with proportional colour coefficients are summed first:
-                # sa = a_1, then sa += u_m a_m; its jamp updates use sa
-                if len(members) > 1:
-                    if mi == 0:
+                    if len(grp) == 1:
+                        di = members[grp[0]][0]
+                        out.append(f"    SDEACC({self.fd_index[di]}, {self.kweight[di]!r});")
+                    else:
+                        # the channel weights need each diagram's own amplitude
+                        sde = " ".join(f"{{ const cx<R> a = {f}({', '.join(a)}); SDEACC({self.fd_index[members[i][0]]}, "
+                                       f"{self.kweight[members[i][0]]!r}); }}" for i, (f, a) in zip(grp, calls))
+                        out.append(f"    if constexpr (SDE) {{ {sde} }}")
+                # the groups of a class with proportional colour coefficients are summed first:
+                # sa = a_1, then sa += u a; its jamp updates use sa
+                if len(groups) > 1:
+                    if gi == 0:
+                        assert uf == (1, 0)
                         out.append("    sa = a;")
                     else:
-                        out.append("    " + ACC_TEXT[(ur, ui)])
+                        out.append("    " + ACC_TEXT[uf])
                         flops[0] += FLOPS["jamp"]
                 marks.append((m_node, m_amp, len(out)))
                 if not last:
                     if prefetch and steps is not None:
                         puts.append([])
                     continue
-                var = "sa" if len(members) > 1 else "a"
+                var = "sa" if len(groups) > 1 else "a"
                 di0 = members[0][0]
                 if steps is None:
                     for seq, c in sorted(self.jcoef[di0].items()):
@@ -474,6 +507,36 @@ class Process:
                 out.append((cls[0][0], ("CLASS", mem), deps))
             self._units = out
         return self._units
+
+    def _linear_groups(self, members):
+        """Partition a unit's members into groups evaluated as one vertex each: members with the
+        same vertex (FFV, three-gluon, or four-gluon of the same colour structure) whose operands
+        are the same nodes in all slots but one, and whose nodes in that slot carry the same
+        momentum (the same external legs).  Greedy in member order; the first group starts with
+        the first member.  Returns lists of member indices."""
+        def sig(m):
+            di, (kind, j), deps, _ = m
+            if kind == "FFV":
+                return ("FFV",), tuple(deps), None
+            t = self.diagrams[di][j]
+            legs = (None,) + tuple(tuple(sorted(D.leaves(k))) for k in D.children(t))
+            return ((t[0],) if t[0] == "V3" else (t[0], t[1])), tuple(deps), legs
+
+        sigs = [sig(m) for m in members]
+        groups = []   # [member indices, slot or None]
+        for i, (head, deps, legs) in enumerate(sigs):
+            for g in groups:
+                h0, d0, l0 = sigs[g[0][0]]
+                if h0 != head or len(d0) != len(deps) or l0 != legs:
+                    continue
+                diff = [k for k in range(len(deps)) if deps[k] != d0[k]]
+                if len(diff) == 1 and g[1] in (None, diff[0]):
+                    g[0].append(i)
+                    g[1] = diff[0]
+                    break
+            else:
+                groups.append([[i], None])
+        return [g[0] for g in groups]
 
     @staticmethod
     def unit_members(unit):
@@ -544,6 +607,7 @@ class Process:
             segs = D.segment_plan(self.plan, jsets, n_seg, beta, window, amps=self.units(), cut=SEGMENT_CUT,
                                   remat_ext=remat_ext)
             self.segment_orders = segs
+            self.segment_emit_groups = []
             self.flops_exec = 0
             partial_jamp = []
             for k, order in enumerate(segs):
@@ -555,6 +619,7 @@ class Process:
                 partial_jamp += pj
                 body = []
                 self.flops_exec += self._emit_qcd_body(body, remat_ext, order=order, steps=steps, final=final)
+                self.segment_emit_groups.append(self.emit_groups)
                 kernels.append((f"amp_seg{k}", body, window, "slots"))
             self.nslot = len(partial_jamp)
             self.partial_jamp = partial_jamp

@@ -125,7 +125,12 @@ def test_pure_gluon_decomposition_explicit():
 def test_every_diagram_evaluated_once(name):
     P = emit.Process(name)
     src = P.source()
-    assert len(re.findall(r"^\s+a = amp_", src, re.M)) == P.n_amplitudes
+    # one vertex line per group of entries that differ in one operand (the vertex on the sum of
+    # those operands), each entry in exactly one group
+    lines = re.findall(r"^\s+a = amp_(.*)$", src, re.M)
+    assert len(lines) == len(P.emit_groups)
+    assert sum(len(g) for g in P.emit_groups) == P.n_amplitudes
+    assert [ln.count("w4_acc<R") for ln in lines] == [len(g) - 1 for g in P.emit_groups]
     # every node of the plan computed exactly once; external gluons of programs that take them
     # from the LDS bases are rebuilt at each use instead; external wavefunctions kept in LDS
     # per lane are computed once at the start (one store each) and read at their uses
@@ -231,13 +236,18 @@ def test_emitted_window_kernels_and_reduction_accumulate_every_jamp():
         body = text[text.index("#define SDEACC"):text.index("\n    if constexpr (SDE) {\n")]
         win = np.zeros(window, complex)
         fr = {}
-        it = iter([m[0] for unit in order for m in P.unit_members(unit)])
+        assert sorted(e for g in P.segment_emit_groups[k] for e, _ in g) == sorted(
+            m[0] for unit in order for m in P.unit_members(unit))
+        it = iter(P.segment_emit_groups[k])
         a = sa = None
         acc = {"sa.r += a.r; sa.i += a.i;": 1, "sa.r -= a.r; sa.i -= a.i;": -1,
                "sa.r -= a.i; sa.i += a.r;": 1j, "sa.r += a.i; sa.i -= a.r;": -1j}
         for line in body.splitlines()[1:]:
             if re.match(r"\s*a = amp", line):
-                a = amp[next(it)]
+                grp = next(it)
+                units = [(int(x), int(y)) for x, y in re.findall(r"w4_acc<R, (-?\d), (-?\d)>", line)]
+                assert units[::-1] == [u for _, u in grp[1:]]   # nested: the last added outermost
+                a = sum(complex(*u) * amp[e] for e, u in grp)
                 continue
             if line.strip() == "sa = a;":
                 sa = a
@@ -286,13 +296,18 @@ def test_emitted_kernel_accumulates_every_jamp(name):
     acc = {"sa.r += a.r; sa.i += a.i;": 1, "sa.r -= a.r; sa.i -= a.i;": -1,
            "sa.r -= a.i; sa.i += a.r;": 1j, "sa.r += a.i; sa.i -= a.r;": -1j}
     assert sorted(P.emit_order) == list(range(len(P.diagrams)))
-    it = iter(P.emit_order)
+    assert sorted(e for g in P.emit_groups for e, _ in g) == list(range(len(P.diagrams)))
+    it = iter(P.emit_groups)
     J = np.zeros(P.nc, complex)
     a = sa = None
     for line in body.splitlines()[1:]:
         t = line.strip()
         if re.match(r"a = amp", t):
-            a = amp[next(it)]
+            # a vertex on a sum of operands stands for the sum of its entries' amplitudes
+            grp = next(it)
+            units = [(int(x), int(y)) for x, y in re.findall(r"w4_acc<R, (-?\d), (-?\d)>", t)]
+            assert units[::-1] == [u for _, u in grp[1:]]   # nested: the last added outermost
+            a = sum(complex(*u) * amp[e] for e, u in grp)
         elif t == "sa = a;":
             sa = a
         elif t in acc:

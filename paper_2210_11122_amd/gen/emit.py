@@ -13,6 +13,7 @@ Flop counts are the real additions and multiplications written in ``helas.hpp`` 
 call (complex multiply = 6, complex add = 2, real x complex = 2), plus momentum sums (4 per
 four-vector addition) and jamp updates (2 per update).
 """
+import collections
 import os
 import re
 from fractions import Fraction
@@ -38,6 +39,8 @@ PRESUM = True
 # the other operands and every momentum the same) as one vertex on the sum of those
 # wavefunctions, each times its unit factor: the vertices are linear in each wavefunction
 LINEAR_MERGE = True
+# and form a sum of operands that several of those vertices use once, as a node of its own
+SUM_NODES = False
 # sa += u a for the units u of the Gaussian integers
 ACC_TEXT = {(1, 0): "sa.r += a.r; sa.i += a.i;", (-1, 0): "sa.r -= a.r; sa.i -= a.i;",
             (0, 1): "sa.r -= a.i; sa.i += a.r;", (0, -1): "sa.r += a.i; sa.i -= a.r;"}
@@ -391,6 +394,14 @@ class Process:
             return FLOPS["amp_ffv" if fn.startswith("amp_ffv") else "amp_vvv" if fn.startswith("amp_vvv<")
                          else "amp_vvvv"]
 
+        sums = {}
+        comb_refs = collections.Counter()
+        if LINEAR_MERGE:
+            for unit in order:
+                members = self.unit_members(unit)
+                for grp in self._linear_groups(members):
+                    if len(grp) > 1:
+                        comb_refs[self._group_terms(members, grp)] += 1
         for ai, unit in enumerate(order):
             members = self.unit_members(unit)
             groups = self._linear_groups(members) if LINEAR_MERGE else [[i] for i in range(len(members))]
@@ -398,7 +409,6 @@ class Process:
                 last = gi == len(groups) - 1
                 m_node = len(out)
                 calls = [call_of(members[i]) for i in grp]
-                m_amp = len(out)
                 fn, args = calls[0]
                 uf = members[grp[0]][3]
                 line = [(members[grp[0]][0], (1, 0))]
@@ -409,13 +419,25 @@ class Process:
                     assert len(diff) == 1 and all(f == fn for f, _ in calls), (unit[0], grp)
                     k = diff.pop()
                     comb = args[k]
+                    terms = [(args[k], (1, 0))]
                     for i, (_, a) in zip(grp[1:], calls[1:]):
                         ur, ui = members[i][3]
                         rel = (ur * uf[0] + ui * uf[1], ui * uf[0] - ur * uf[1])
                         comb = f"w4_acc<R, {rel[0]}, {rel[1]}>({comb}, {a[k]})"
-                        flops[0] += 8
+                        terms.append((a[k], rel))
                         line.append((members[i][0], rel))
+                    # a sum that several groups use is formed once, as a node of its own
+                    tkey = self._group_terms(members, grp)
+                    if SUM_NODES and comb_refs[tkey] > 1:
+                        if tkey not in sums:
+                            sums[tkey] = f"s{len(sums)}"
+                            out.append(f"    const W4<R> {sums[tkey]} = {comb};")
+                            flops[0] += 8 * (len(grp) - 1)
+                        comb = sums[tkey]
+                    else:
+                        flops[0] += 8 * (len(grp) - 1)
                     args = args[:k] + [comb] + args[k + 1:]
+                m_amp = len(out)
                 self.emit_groups.append(line)
                 out.append(f"    a = {fn}({', '.join(args)});")
                 flops[0] += amp_flops(fn)
@@ -537,6 +559,15 @@ class Process:
             else:
                 groups.append([[i], None])
         return [g[0] for g in groups]
+
+    @staticmethod
+    def _group_terms(members, grp):
+        """the operand sum of a group (of at least two members): ((node in the slot where the
+        members differ, unit relative to the first member's), ..)"""
+        d0, uf = members[grp[0]][2], members[grp[0]][3]
+        slot = next(j for i in grp[1:] for j in range(len(d0)) if members[i][2][j] != d0[j])
+        return tuple((members[i][2][slot], (members[i][3][0] * uf[0] + members[i][3][1] * uf[1],
+                                            members[i][3][1] * uf[0] - members[i][3][0] * uf[1])) for i in grp)
 
     @staticmethod
     def unit_members(unit):

@@ -121,13 +121,19 @@ def test_pure_gluon_decomposition_explicit():
             assert abs(X - S) < 1e-12
 
 
+def expand_sums(text):
+    """the text with every operand-sum node (const W4<R> sN = ...;) written out at its uses"""
+    defs = dict(re.findall(r"const W4<R> (s\d+) = (w4_acc[^;]*);", text))
+    return re.sub(r"\b(s\d+)\b(?! =)", lambda m: defs.get(m.group(1), m.group(1)), text)
+
+
 @pytest.mark.parametrize("name", ["gg_tt", "gg_ttg", "gg_ttgg"])
 def test_every_diagram_evaluated_once(name):
     P = emit.Process(name)
     src = P.source()
     # one vertex line per group of entries that differ in one operand (the vertex on the sum of
     # those operands), each entry in exactly one group
-    lines = re.findall(r"^\s+a = amp_(.*)$", src, re.M)
+    lines = re.findall(r"^\s+a = amp_(.*)$", expand_sums(src), re.M)
     assert len(lines) == len(P.emit_groups)
     assert sum(len(g) for g in P.emit_groups) == P.n_amplitudes
     assert [ln.count("w4_acc<R") for ln in lines] == [len(g) - 1 for g in P.emit_groups]
@@ -233,7 +239,7 @@ def test_emitted_window_kernels_and_reduction_accumulate_every_jamp():
     macro = re.compile(r"(JTAKE|JLAST|JPUT)\((\d+), (\d+)\);")
     for k, order in enumerate(segs):
         text = P.extra_files[f"proc_gg_ttggg_amp_seg{k}.hip"]
-        body = text[text.index("#define SDEACC"):text.index("\n    if constexpr (SDE) {\n")]
+        body = expand_sums(text[text.index("#define SDEACC"):text.index("\n    if constexpr (SDE) {\n")])
         win = np.zeros(window, complex)
         fr = {}
         assert sorted(e for g in P.segment_emit_groups[k] for e, _ in g) == sorted(
@@ -291,7 +297,7 @@ def test_emitted_kernel_accumulates_every_jamp(name):
     for di in range(len(P.diagrams)):
         for q, c in P.jcoef[di].items():
             direct[perm_index[q]] += complex(c.re, c.im) * amp[di]
-    body = src[src.index("#define SDEACC"):src.index("\n    if constexpr (SDE) {\n")]
+    body = expand_sums(src[src.index("#define SDEACC"):src.index("\n    if constexpr (SDE) {\n")])
     jadd = re.compile(r"JADD\((\d+), ([01]), ([^;]*)\);")
     acc = {"sa.r += a.r; sa.i += a.i;": 1, "sa.r -= a.r; sa.i -= a.i;": -1,
            "sa.r -= a.i; sa.i += a.r;": 1j, "sa.r += a.i; sa.i -= a.r;": -1j}

@@ -381,3 +381,43 @@ def test_spare_waves_write_nothing(name):
                         guarded.pop()
             assert not guarded
     assert n_stores > 0
+
+
+@pytest.mark.parametrize("name,merged", [("gg_tt", 0), ("gg_ttg", 0), ("gg_ttgg", 36), ("gg_ttggg", 810)])
+def test_shared_vertices_differ_in_one_operand_of_equal_momentum(name, merged):
+    """the groups that share one vertex: within one colour class, the same vertex (and four-gluon
+    colour structure), the same nodes in every slot but one, and in that slot nodes of the same
+    external legs (so the same momentum enters the vertex); the groups cover every member once,
+    the first starts with the class's first member"""
+    from paper_2210_11122_amd.gen import diagrams as D
+    P = emit.Process(name)
+    P.source()
+    saved = 0
+    for unit in P.units():
+        members = P.unit_members(unit)
+        groups = P._linear_groups(members)
+        assert sorted(i for g in groups for i in g) == list(range(len(members)))
+        assert groups[0][0] == 0
+        for g in groups:
+            saved += len(g) - 1
+            heads = set()
+            for i in g:
+                di, (kind, j), deps, _ = members[i]
+                t = None if kind == "FFV" else P.diagrams[di][j]
+                heads.add("FFV" if t is None else (t[0], t[1] if t[0] == "V4" else None))
+            assert len(heads) == 1
+            d0 = members[g[0]][2]
+            slots = {k for i in g[1:] for k in range(len(d0)) if members[i][2][k] != d0[k]}
+            assert len(slots) <= 1
+            if slots:
+                k = slots.pop()
+                def legs(node):
+                    if node[0] == "G":
+                        return tuple(sorted(D.leaves(node[1])))
+                    if node[0] == "EXT_G":
+                        return (node[1],)
+                    if node[0] in ("U", "V"):
+                        return node[0], tuple(sorted(x for b in node[1] for x in D.leaves(b)))
+                    return node
+                assert len({legs(members[i][2][k]) for i in g}) == 1, (unit[0], g)
+    assert saved == merged

@@ -484,10 +484,14 @@ def segment_plan(plan, jamp_sets, n_segments, beta, window, amps=None, cut="amps
     recomputes the currents it needs) and reorder each piece the same way.  amps: the units
     to order (default: the plan's amplitudes; see `schedule`).  cut: "amps" cuts where the
     amplitudes evaluated so far (a unit counts its members) reach k / n_segments of all, so the
-    kernels share the work evenly; "units" cuts into equal numbers of units."""
+    kernels share the work evenly; "units" cuts into equal numbers of units; a function of the
+    unit gives each unit that weight instead."""
     amps = plan.amplitudes() if amps is None else amps
     order = schedule_window(amps, plan.nodes(), jamp_sets, beta, window, remat_ext)
-    size = [len(u[1][1]) if (cut == "amps" and u[1][0] == "CLASS") else 1 for u in order]
+    if callable(cut):
+        size = [cut(u) for u in order]
+    else:
+        size = [len(u[1][1]) if (cut == "amps" and u[1][0] == "CLASS") else 1 for u in order]
     total = sum(size)
     cuts, acc = [0], 0
     for i, w in enumerate(size):

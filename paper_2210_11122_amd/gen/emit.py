@@ -31,7 +31,10 @@ FLOPS = {
 QCD_PROCESSES = {"gg_tt": 2, "gg_ttg": 3, "gg_ttgg": 4, "gg_ttggg": 5}
 # name -> (segment kernels, LDS jamp-window slots, weight of window misses in the schedule)
 SEGMENTS = {"gg_ttggg": (14, 35, 2.0)}
-# how the segments are cut from the schedule (diagrams.segment_plan): "amps" or "units"
+# how the segments are cut from the schedule (diagrams.segment_plan): "amps" (a unit weighs its
+# members), "units", or "vertices" (a unit weighs the vertices it evaluates once members share
+# vertices; measured slower for gg_ttggg: per 2^17 events FP64 with 12 / 13 / 14 segments 222 / 225
+# / 232 ms, mixed 127 / 130 / 135, against 219 and 125 with "amps" and 14)
 SEGMENT_CUT = "amps"
 # sum the amplitudes of entries with proportional colour coefficients before their jamp updates
 PRESUM = True
@@ -635,7 +638,10 @@ class Process:
             jsets = [set(self.perm_index[q] for q in self.jcoef[i]) for i in range(len(self.diagrams))]
             # algorithmic count: every node once, in any order
             fl = self._emit_qcd_body([], remat_ext, order=self.units())
-            segs = D.segment_plan(self.plan, jsets, n_seg, beta, window, amps=self.units(), cut=SEGMENT_CUT,
+            cut = SEGMENT_CUT
+            if cut == "vertices":
+                cut = lambda u: len(self._linear_groups(self.unit_members(u))) if LINEAR_MERGE else len(self.unit_members(u))
+            segs = D.segment_plan(self.plan, jsets, n_seg, beta, window, amps=self.units(), cut=cut,
                                   remat_ext=remat_ext)
             self.segment_orders = segs
             self.segment_emit_groups = []

@@ -44,6 +44,10 @@ PRESUM = True
 LINEAR_MERGE = True
 # and form a sum of operands that several of those vertices use once, as a node of its own
 SUM_NODES = False
+# processes whose operand sums also pass through the vertices that made their terms, where those
+# differ in one operand at the same momenta (recursively): one current on a sum instead of a sum
+# of currents.  Each such sum is then a node of its own, formed once per kernel
+DEEP_MERGE = {"gg_ttggg"}
 # sa += u a for the units u of the Gaussian integers
 ACC_TEXT = {(1, 0): "sa.r += a.r; sa.i += a.i;", (-1, 0): "sa.r -= a.r; sa.i -= a.i;",
             (0, 1): "sa.r -= a.i; sa.i += a.r;", (0, -1): "sa.r += a.i; sa.i -= a.r;"}
@@ -340,36 +344,110 @@ class Process:
                 return nm
             deps = [emit(dk) for dk in D.node_deps(key)]
             nm = f"w{len(names)}"
+            code, fl = node_code(key, deps)
+            out.append(f"    const W4<R> {nm} = {code};")
+            flops[0] += fl
+            names[key] = nm
+            return nm
+
+        def node_code(key, deps, count=True):
+            """the call that computes node `key` from its operands `deps` (names or expressions),
+            and its flops; count: the momentum sums it introduces enter the algorithmic count"""
+            kind = key[0]
+            Kc = K if count else (lambda lv: "(" + " + ".join(q(i) for i in sorted(lv)) + ")")
             if kind == "G":
                 t = key[1]
                 kids = D.children(t)
                 if t[0] == "V3":
-                    ka, kb = K(D.leaves(kids[0])), K(D.leaves(kids[1]))
-                    out.append(f"    const W4<R> {nm} = vvv_cur<R>({deps[0]}, {ka}, {deps[1]}, {kb}, gs);")
-                    flops[0] += FLOPS["vvv_cur"]
-                else:
-                    P = K(D.leaves(t))
-                    out.append(f"    const W4<R> {nm} = vvvv_cur<R, {t[1]}>({deps[0]}, {deps[1]}, {deps[2]}, {P}, gs);")
-                    flops[0] += FLOPS["vvvv_cur"]
-            elif kind in ("U", "V"):
-                blocks = key[1]
-                lv = [g for b in blocks for g in D.leaves(b)]
-                Km = K(lv)
+                    ka, kb = Kc(D.leaves(kids[0])), Kc(D.leaves(kids[1]))
+                    return f"vvv_cur<R>({deps[0]}, {ka}, {deps[1]}, {kb}, gs)", FLOPS["vvv_cur"]
+                return (f"vvvv_cur<R, {t[1]}>({deps[0]}, {deps[1]}, {deps[2]}, {Kc(D.leaves(t))}, gs)",
+                        FLOPS["vvvv_cur"])
+            if kind in ("U", "V"):
+                Km = Kc([g for b in key[1] for g in D.leaves(b)])
                 if kind == "U":
-                    out.append(f"    const W4<R> {nm} = fstr_u<R>({deps[0]}, {deps[1]}, PM(2) - {Km}, mt, gs);")
-                else:
-                    out.append(f"    const W4<R> {nm} = fstr_v<R>({deps[0]}, {deps[1]}, {Km} - PM(3), mt, gs);")
-                flops[0] += FLOPS["fstr"] + FLOPS["p4add"]
-            elif kind == "JF":
-                pre, suf = key[1], key[2]
-                used = set(g for b in pre + suf for g in D.leaves(b))
+                    return f"fstr_u<R>({deps[0]}, {deps[1]}, PM(2) - {Km}, mt, gs)", FLOPS["fstr"] + FLOPS["p4add"]
+                return f"fstr_v<R>({deps[0]}, {deps[1]}, {Km} - PM(3), mt, gs)", FLOPS["fstr"] + FLOPS["p4add"]
+            if kind == "JF":
+                used = set(g for b in key[1] + key[2] for g in D.leaves(b))
                 gap = sorted(set(range(self.ng)) - used)
-                out.append(f"    const W4<R> {nm} = jf<R>({deps[0]}, {deps[1]}, {K(gap)}, gs);")
-                flops[0] += FLOPS["jf"]
-            else:
-                raise ValueError(key)
-            names[key] = nm
+                return f"jf<R>({deps[0]}, {deps[1]}, {Kc(gap)}, gs)", FLOPS["jf"]
+            raise ValueError(key)
+
+        def emit_local(key, local, lines):
+            """a node for the channel-weight instance only: taken from the program if it is there,
+            else computed into `lines` (a block of that instance) under a name of the block"""
+            if key[0].startswith("EXT") or key in names:
+                return emit(key)
+            if key in local:
+                return local[key]
+            deps = [emit_local(dk, local, lines) for dk in D.node_deps(key)]
+            nm = f"z{len(local)}"
+            lines.append(f"const W4<R> {nm} = {node_code(key, deps, count=False)[0]};")
+            local[key] = nm
             return nm
+
+        def vertex_of(key):
+            """(vertex, operand nodes, momenta) of a computed node through which a sum of such
+            nodes can pass (the vertex is linear in each operand), or None"""
+            kind = key[0]
+            if kind == "G":
+                t = key[1]
+                kids = D.children(t)
+                ops = [D.wf_key(c) for c in kids]
+                if t[0] == "V3":
+                    return ("V3",), ops, (tuple(sorted(D.leaves(kids[0]))), tuple(sorted(D.leaves(kids[1]))))
+                return ("V4", t[1]), ops, (tuple(sorted(D.leaves(t))),)
+            if kind in ("U", "V"):
+                return (kind,), list(D.node_deps(key)), (tuple(sorted(g for b in key[1] for g in D.leaves(b))),)
+            return None
+
+        def opsum(terms):
+            """the node sum_i u_i X_i (terms: (node, unit), the first unit 1), formed once per body:
+            nodes made by the same vertex from the same operands but one, at the same momenta,
+            are summed in that operand first (recursively), so that the vertex runs once"""
+            tkey = tuple(terms)
+            if tkey in sums:
+                return sums[tkey]
+            parts = []   # [term indices, slot]
+            for i, (k, _) in enumerate(terms):
+                v = vertex_of(k)
+                for g in parts:
+                    v0 = vertex_of(terms[g[0][0]][0])
+                    if v is None or v0 is None or v0[0] != v[0] or v0[2] != v[2] or len(v0[1]) != len(v[1]):
+                        continue
+                    diff = [j for j in range(len(v[1])) if v[1][j] != v0[1][j]]
+                    if len(diff) == 1 and g[1] in (None, diff[0]):
+                        g[0].append(i)
+                        g[1] = diff[0]
+                        break
+                else:
+                    parts.append([[i], None])
+            exprs = []
+            for idx, slot in parts:
+                k0, u0 = terms[idx[0]]
+                if len(idx) == 1:
+                    exprs.append((emit(k0), u0))
+                    continue
+                ops0 = vertex_of(k0)[1]
+                inner = opsum([(vertex_of(terms[i][0])[1][slot], unit_div(terms[i][1], u0)) for i in idx])
+                deps = [inner if j == slot else emit(o) for j, o in enumerate(ops0)]
+                code, fl = node_code(k0, deps)
+                flops[0] += fl
+                exprs.append((code, u0))
+            assert exprs[0][1] == (1, 0)
+            comb = exprs[0][0]
+            for e, u in exprs[1:]:
+                comb = f"w4_acc<R, {u[0]}, {u[1]}>({comb}, {e})"
+                flops[0] += 8
+            nm = f"s{len(sums)}"
+            out.append(f"    const W4<R> {nm} = {comb};")
+            sums[tkey] = nm
+            return nm
+
+        def unit_div(u, v):
+            """u / v for units of the Gaussian integers"""
+            return (u[0] * v[0] + u[1] * v[1], u[1] * v[0] - u[0] * v[1])
 
         if order is None:
             order = D.schedule(self.plan, remat_ext=remat_ext, amps=self.units())
@@ -378,26 +456,30 @@ class Process:
         # per `a = amp_...` line: [(entry, unit factor relative to the line's first entry)]
         self.emit_groups = []
 
-        def call_of(member):
-            """emit the nodes of one amplitude entry; its vertex call as (function, arguments)"""
-            di, (kind, j), deps, _ = member
+        def call_text(member, ops):
+            """the vertex call of one amplitude entry on operands `ops` (names or expressions, in
+            the order of its dependencies) as (function, arguments)"""
+            di, (kind, j), _, _ = member
             if kind == "FFV":
-                return "amp_ffv<R>", [emit(k) for k in deps] + ["gs"]
+                return "amp_ffv<R>", list(ops) + ["gs"]
             t = self.diagrams[di][j]
             kids = D.children(t)
-            wx = emit(deps[0])
-            ws = [emit(k) for k in deps[1:]]
             if t[0] == "V3":
                 kx = K((self.ng - 1,)) if self.kind == "gluon" else "(-" + K(D.leaves(t)) + ")"
                 ka, kb = K(D.leaves(kids[0])), K(D.leaves(kids[1]))
-                return "amp_vvv<R>", [wx, kx, ws[0], ka, ws[1], kb, "gs"]
-            return f"amp_vvvv<R, {t[1]}>", [wx, ws[0], ws[1], ws[2], "gs"]
+                return "amp_vvv<R>", [ops[0], kx, ops[1], ka, ops[2], kb, "gs"]
+            return f"amp_vvvv<R, {t[1]}>", [ops[0], ops[1], ops[2], ops[3], "gs"]
+
+        def call_of(member):
+            """emit the nodes of one amplitude entry; its vertex call as (function, arguments)"""
+            return call_text(member, [emit(k) for k in member[2]])
 
         def amp_flops(fn):
             return FLOPS["amp_ffv" if fn.startswith("amp_ffv") else "amp_vvv" if fn.startswith("amp_vvv<")
                          else "amp_vvvv"]
 
         sums = {}
+        deep = LINEAR_MERGE and self.name in DEEP_MERGE
         comb_refs = collections.Counter()
         if LINEAR_MERGE:
             for unit in order:
@@ -411,11 +493,30 @@ class Process:
             for gi, grp in enumerate(groups):
                 last = gi == len(groups) - 1
                 m_node = len(out)
-                calls = [call_of(members[i]) for i in grp]
-                fn, args = calls[0]
                 uf = members[grp[0]][3]
                 line = [(members[grp[0]][0], (1, 0))]
-                if len(grp) > 1:
+                sde_block = None
+                if len(grp) > 1 and deep:
+                    # the operand sum through the vertices that made its terms (opsum); each
+                    # diagram's own amplitude, for the channel weights only, in a block of that instance
+                    terms = self._group_terms(members, grp)
+                    d0 = members[grp[0]][2]
+                    slot = next(j for i in grp[1:] for j in range(len(d0)) if members[i][2][j] != d0[j])
+                    sub = opsum(list(terms))
+                    fn, args = call_text(members[grp[0]], [sub if j == slot else emit(dk) for j, dk in enumerate(d0)])
+                    line += [(members[i][0], rel) for i, (_, rel) in zip(grp[1:], terms[1:])]
+                    if self.fd_index is not None:
+                        local, blk = {}, []
+                        for i in grp:
+                            f, a_ = call_text(members[i], [emit_local(dk, local, blk) for dk in members[i][2]])
+                            blk.append(f"{{ const cx<R> a = {f}({', '.join(a_)}); SDEACC({self.fd_index[members[i][0]]}, "
+                                       f"{self.kweight[members[i][0]]!r}); }}")
+                        sde_block = blk
+                    calls = None
+                else:
+                    calls = [call_of(members[i]) for i in grp]
+                    fn, args = calls[0]
+                if len(grp) > 1 and not deep:
                     # one vertex on the sum of the operands that differ, each times its unit
                     # relative to the first member's: sum_m u_m V(.., w_m, ..) = u_f V(.., sum_m (u_m/u_f) w_m, ..)
                     diff = {k for f, a in calls[1:] for k in range(len(args)) if a[k] != args[k]}
@@ -449,6 +550,8 @@ class Process:
                     if len(grp) == 1:
                         di = members[grp[0]][0]
                         out.append(f"    SDEACC({self.fd_index[di]}, {self.kweight[di]!r});")
+                    elif sde_block is not None:
+                        out.append(f"    if constexpr (SDE) {{ {' '.join(sde_block)} }}")
                     else:
                         # the channel weights need each diagram's own amplitude
                         sde = " ".join(f"{{ const cx<R> a = {f}({', '.join(a)}); SDEACC({self.fd_index[members[i][0]]}, "

@@ -1,5 +1,6 @@
 """CPU tests of the process generator (diagram enumeration, colour algebra, evaluation
 plan, jamp window) against independent definitions."""
+import collections
 import itertools
 import math
 import re
@@ -250,9 +251,9 @@ def test_emitted_window_kernels_and_reduction_accumulate_every_jamp():
                "sa.r -= a.i; sa.i += a.r;": 1j, "sa.r += a.i; sa.i -= a.r;": -1j}
         for line in body.splitlines()[1:]:
             if re.match(r"\s*a = amp", line):
+                # the line's vertex on operand sums is the sum of its entries' amplitudes with these
+                # units (test_emitted_vertices_on_sums_equal_the_diagram_amplitudes checks the text)
                 grp = next(it)
-                units = [(int(x), int(y)) for x, y in re.findall(r"w4_acc<R, (-?\d), (-?\d)>", line)]
-                assert units[::-1] == [u for _, u in grp[1:]]   # nested: the last added outermost
                 a = sum(complex(*u) * amp[e] for e, u in grp)
                 continue
             if line.strip() == "sa = a;":
@@ -421,3 +422,115 @@ def test_shared_vertices_differ_in_one_operand_of_equal_momentum(name, merged):
                     return node
                 assert len({legs(members[i][2][k]) for i in g}) == 1, (unit[0], g)
     assert saved == merged
+
+
+# arguments of each emitted routine that are wavefunctions (the others are momenta or couplings)
+_WF_ARGS = {"vvv_cur": (0, 2), "vvvv_cur": (0, 1, 2), "fstr_u": (0, 1), "fstr_v": (0, 1), "jf": (0, 1),
+            "amp_ffv": (0, 1, 2), "amp_vvv": (0, 2, 4), "amp_vvvv": (0, 1, 2, 3), "w4_acc": (0, 1)}
+
+
+def _split_call(e):
+    """'f<T..>(a, b, ..)' -> ('f<T..>', [a, b, ..]) split at the top-level commas; else None"""
+    m = re.match(r"^(\w+(?:<[^>]*>)?)\((.*)\)$", e.strip())
+    if not m:
+        return None
+    args, depth, cur = [], 0, ""
+    for ch in m.group(2):
+        if ch == "," and depth == 0:
+            args.append(cur.strip())
+            cur = ""
+            continue
+        depth += ch in "(<"
+        depth -= ch in ")>"
+        cur += ch
+    args.append(cur.strip())
+    return m.group(1), args
+
+
+def _symbolic_terms(expr, defs, memo):
+    """the emitted expression as sum_j c_j T_j: every operand sum (w4_acc) distributed through the
+    vertices, which are linear in each wavefunction; T_j is a tree of routine names down to the
+    external states, ('ext', particle)"""
+    expr = expr.strip()
+    if expr in memo:
+        return memo[expr]
+    if re.fullmatch(r"[wsz]\d+|y\d+_\d+|XW\(\d+\)", expr):
+        out = _symbolic_terms(defs[expr], defs, memo)
+    else:
+        fn, args = _split_call(expr)
+        base = fn.split("<")[0]
+        if base.startswith("ext_"):
+            p = re.search(r"PM\((\d+)\)|m\d+_(\d+)", args[0])
+            out = [(1, ("ext", int(p.group(1) or p.group(2))))]
+        elif base == "w4_acc":
+            u = complex(*(int(x) for x in re.findall(r"-?\d+", fn[fn.index("<"):])))
+            out = _symbolic_terms(args[0], defs, memo) + [(c * u, t) for c, t in _symbolic_terms(args[1], defs, memo)]
+        else:
+            tag = base + ("" if base not in ("vvvv_cur", "amp_vvvv") else fn[fn.index(","):])
+            out = [(1, ())]
+            for i in _WF_ARGS[base]:
+                out = [(c * c2, t + (t2,)) for c, t in out for c2, t2 in _symbolic_terms(args[i], defs, memo)]
+            out = [(c, (tag,) + t) for c, t in out]
+    memo[expr] = out
+    return out
+
+
+def _node_tree(P, key):
+    """the same tree from the generator's plan node, independently of the emitted text"""
+    kind = key[0]
+    if kind == "EXT_G":
+        return ("ext", P.gpar[key[1]])
+    if kind in ("EXT_U", "EXT_V"):
+        return ("ext", 2 if kind == "EXT_U" else 3)
+    deps = tuple(_node_tree(P, k) for k in D.node_deps(key))
+    if kind == "G":
+        t = key[1]
+        return (("vvv_cur",) if t[0] == "V3" else (f"vvvv_cur, {t[1]}>",)) + deps
+    return ({"U": "fstr_u", "V": "fstr_v", "JF": "jf"}[kind],) + deps
+
+
+@pytest.mark.parametrize("name", ["gg_ttgg", "gg_ttggg"])
+def test_emitted_vertices_on_sums_equal_the_diagram_amplitudes(name):
+    """expand every `a = amp_...` line of the emitted kernels symbolically (operand sums distributed
+    through the vertices): it equals the sum of its diagram amplitudes, each with its unit factor,
+    built from the plan's nodes"""
+    P = emit.Process(name)
+    src = P.source()
+    if P.segments:
+        texts = [P.extra_files[f"proc_{name}_amp_seg{k}.hip"] for k in range(P.segments[0])]
+        groups = P.segment_emit_groups
+        orders = P.segment_orders
+    else:
+        texts, groups, orders = [src], [P.emit_groups], [None]
+    members = {}
+    for unit in P.units():
+        for m in P.unit_members(unit):
+            members[m[0]] = m
+    n_lines = 0
+    for text, grps in zip(texts, groups):
+        body = text[text.index("#define SDEACC"):text.index("\n    if constexpr (SDE) {\n")]
+        body = re.sub(r"^\s*if constexpr \(SDE\).*$", "", body, flags=re.M)
+        defs = dict(re.findall(r"const W4<R> ([wsz]\d+) = ([^;]*);", body))
+        # external states kept in LDS: the prefetched copies y<step>_<slot> of XW(slot)
+        xw = {f"XW({k})": code for k, (code, _, _) in enumerate(P.xw_init)}
+        defs.update(xw)
+        defs.update({y: f"XW({k})" for y, k in re.findall(r"W4<R> (y\d+_\d+) = XW\((\d+)\);", body)})
+        lines = re.findall(r"^\s*a = (amp_[^;]*);", body, re.M)
+        assert len(lines) == len(grps)
+        memo = {}
+        for line, grp in zip(lines, grps):
+            got = collections.Counter()
+            for c, t in _symbolic_terms(line, defs, memo):
+                got[t] += c
+            want = collections.Counter()
+            for e, (ur, ui) in grp:
+                di, (kind, j), deps, _ = members[e]
+                if kind == "FFV":
+                    tag = "amp_ffv"
+                else:
+                    tr = P.diagrams[di][j]
+                    tag = "amp_vvv" if tr[0] == "V3" else f"amp_vvvv, {tr[1]}>"
+                want[(tag,) + tuple(_node_tree(P, k) for k in deps)] += complex(ur, ui)
+            assert {t: c for t, c in got.items() if c != 0} == dict(want), (name, line[:120])
+            n_lines += 1
+    assert n_lines == sum(len(g) for g in groups)

@@ -109,6 +109,14 @@ LANE_PER_EVENT = {"ee_mumu", "ee_mumu_z"}
 # the batch size from which calls take that kernel (smaller batches fill the GPU only with a
 # wave per helicity)
 LANE_MIN_EVENTS = 1 << 16
+# in that kernel, compute each external state for both helicities once per event, before the
+# helicity loop, which then selects them (instead of computing them for every helicity): ee_mumu
+# at 2^20 events FP64 82 -> 77 us per call, mixed FP16 89 -> 79 us
+LANE_HOIST_EXT = True
+# minimum waves per SIMD asked of that kernel (FP64, FP32): the eight hoisted FP64 states take 128
+# registers.  Measured with the hoisted states: FP64 77 us at two waves, 79 at three; FP32 90 us at
+# two, 79 at three
+LANE_MIN_WAVES = (2, 3)
 ALL_PROCESSES = ["ee_mumu", "gg_tt", "gg_ttg", "gg_ttgg", "gg_ttggg", "gg_gg", "ee_mumu_z"]
 # electroweak constants of ee -> mumu with Z exchange: M_Z, Gamma_Z, M_W [GeV]
 EW_MZ, EW_WZ, EW_MW = 91.188, 2.441404, 80.419
@@ -1137,7 +1145,8 @@ class Process:
             raise ValueError("the lane-per-event kernel handles one colour flow")
         L = []
         L.append("template <class R>")
-        L.append("__global__ __launch_bounds__(64, 4) void amp_lanes(const double* __restrict__ mom, int64_t n_evt, "
+        L.append(f"__global__ __launch_bounds__(64, sizeof(R) == 8 ? {LANE_MIN_WAVES[0]} : {LANE_MIN_WAVES[1]}) void amp_lanes("
+                 "const double* __restrict__ mom, int64_t n_evt, "
                  "const signed char* __restrict__ hel, int n_good, double gs, FusedColour fc)")
         L.append("{")
         L.append("    __shared__ double lds[4 * NPAR * 64];")
@@ -1150,6 +1159,19 @@ class Process:
         L.append("#define PM(i) lds_p4(lds, i, lane)")
         L.append("#define SDEACC(d, k) do { } while (0)")
         L.append("#define JADD(s, ri, v) (Jr[2 * (s) + (ri)] += (v))")
+        if LANE_HOIST_EXT:
+            # each external state for both helicities, once per event; the loop selects
+            ext = re.compile(r"^\s*const W4<R> (w\d+) = (ext_\w+<R>)\((PM\(\d+\)), ([^,]+), lam\[(\d+)\]\);$")
+            kept = []
+            for ln in body:
+                m = ext.match(ln)
+                if not m:
+                    kept.append(ln)
+                    continue
+                w, fn, pm, mass, i = m.groups()
+                L.append(f"    const W4<R> {w}_p = {fn}({pm}, {mass}, 1), {w}_m = {fn}({pm}, {mass}, -1);")
+                kept.append(f"    const W4<R> {w} = lam[{i}] > 0 ? {w}_p : {w}_m;")
+            body = kept
         L.append("    double s = 0.0, m = 0.0;")
         L.append("    int in_group = 0;")
         L.append("#pragma unroll 1")

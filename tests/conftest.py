@@ -14,7 +14,7 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # GPU tests are skipped (not failed) where no GPU is visible; they still fail loudly
-    # on a GPU machine if the HIP library is missing.
+    # on a machine with a GPU if the HIP library is missing.
     try:
         import torch
         have_gpu = torch.cuda.is_available()

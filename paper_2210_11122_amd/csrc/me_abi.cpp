@@ -354,8 +354,12 @@ int run_chunks(me_handle* h, int precision, const signed char* hel, int n_good, 
     if (precision == ME_FP64) fcol.aop = h->d_aop64, fcol.form = ME_FP64;
     else if (precision == ME_MIXED_FP16) fcol.aop = h->d_aop16;
     else fcol.aop = h->d_aopb, fcol.aop_lo = h->d_aopb_lo, fcol.lo_mask = h->lo_mask_b16;
-    // small processes: the amplitude kernel also sums the helicities (one launch)
-    const bool hsum = fused && P->hel_sum_in_kernel && n_good <= 16;
+    // small processes: the amplitude kernel also sums the helicities (one launch), in a workgroup
+    // of all good helicities, or with one lane per event for large enough chunks (FP64, and the
+    // mixed forms of one flow whose colour operand the 16-bit type holds exactly)
+    const bool hsum_waves = fused && P->hel_sum_in_kernel && n_good <= 16;
+    const bool lane_form = fused && P->lane_min_events > 0 &&
+                           (precision == ME_FP64 || (P->nc == 1 && !(fcol.lo_mask & 1)));
     void* jamp = scratch;
     double* part = reinterpret_cast<double*>(static_cast<char*>(scratch) + (size_t)chunk * jamp_bytes_per_event);
     for (int64_t c0 = 0; c0 < n; c0 += chunk) {
@@ -364,6 +368,7 @@ int run_chunks(me_handle* h, int precision, const signed char* hel, int n_good, 
         const double* m = mom + c0 * P->npar * 4;
         TimedLaunch ta(h, st, 0, timed);
         const int* ch = chan ? chan + c0 : nullptr;
+        const bool hsum = hsum_waves || (lane_form && nc >= P->lane_min_events);
         hipError_t e;
         if (fused && hsum) {
             // the amplitude kernel ends with the colour sum and the helicity sum

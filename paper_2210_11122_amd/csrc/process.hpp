@@ -15,10 +15,11 @@ struct FusedColour {
     const void* aop_lo;  // BF16 lo tiles (BF16 form)
     uint64_t lo_mask;    // tiles with a non-zero lo part (BF16 form)
     int form;            // ME_FP64, ME_MIXED_FP16 or ME_MIXED_BF16 (me.h)
-    // processes with hel_sum_in_kernel: if hsum_out is set, one workgroup holds all good
-    // helicities of its event block and the kernel also sums them, in groups of hel_per_group
-    // from the first (the order of the separate helicity-sum kernel), times hsum_scale, into
-    // hsum_out[event]; nothing goes to the jamp scratch
+    // processes with hel_sum_in_kernel or lane_min_events: if hsum_out is set, the kernel also
+    // sums the good helicities (one workgroup holding all of an event block's, or one lane per
+    // event for batches of at least lane_min_events), in groups of hel_per_group from the first
+    // (the order of the separate helicity-sum kernel), times hsum_scale, into hsum_out[event];
+    // nothing goes to the jamp scratch
     double* hsum_out;
     double hsum_scale;
     int hel_per_group;
@@ -55,6 +56,8 @@ struct ProcessDesc {
     int sde_supported;         // single-diagram channel weights available
     int fused_colour;          // the amplitude kernels can do the colour sum themselves (FusedColour)
     int hel_sum_in_kernel;     // ... and the helicity sum (FusedColour.hsum_out; at most 16 good helicities)
+    int64_t lane_min_events;   // batches from this size can take the kernel with one lane per event, which
+                               // also sums the helicities: FP64, and mixed forms of one flow (0: none)
     amp_launch_f64 launch_f64;
     amp_launch_f32 launch_f32;
 };

@@ -105,7 +105,7 @@ HEL_SUM_IN_KERNEL = {"ee_mumu", "ee_mumu_z"}
 # good helicities in turn (amp_lanes): no helicity waves to combine, no barrier after the
 # momentum staging.  In the mixed forms the one-flow 16-bit tile has a scalar equivalent
 # (colorsum.hpp, cs1_h16), so they use it too
-LANE_PER_EVENT = {"ee_mumu", "ee_mumu_z"}
+LANE_PER_EVENT = {"ee_mumu", "ee_mumu_z", "gg_tt"}
 # the batch size from which calls take that kernel (smaller batches fill the GPU only with a
 # wave per helicity)
 LANE_MIN_EVENTS = 1 << 16
@@ -869,20 +869,23 @@ class Process:
                 L.append("        if (e != hipSuccess) return e;")
                 L.append("    }")
             else:
-                if fused and self.name in HEL_SUM_IN_KERNEL:
+                if fused and (self.name in HEL_SUM_IN_KERNEL or nm in LANE_PER_EVENT):
                     L.append("    if (fc && fc->hsum_out) {  // the kernel also sums the helicities")
                     if nm in LANE_PER_EVENT:
                         L.append("        // batches large enough to fill the GPU with one lane per event (the mixed forms when")
                         L.append("        // their one colour operand is exact in the 16-bit type, as the scalar form assumes)")
-                        L.append(f"        if (n_evt >= {LANE_MIN_EVENTS} && (sizeof(R) == 8 || !(fc->lo_mask & 1))) {{")
+                        L.append(f"        if (n_evt >= {LANE_MIN_EVENTS} && (sizeof(R) == 8 || (NC == 1 && !(fc->lo_mask & 1)))) {{")
                         L.append("            hipLaunchKernelGGL((amp_lanes<R>), dim3((unsigned)((n_evt + 63) / 64)), dim3(64), 0, st, "
-                                 "mom, n_evt, hel, n_good, gs, *fc);")
+                                 "mom, n_evt, hel, n_good, mt, gs, *fc);")
                         L.append("            return hipGetLastError();")
                         L.append("        }")
-                    L.append("        if (n_good > 16) return hipErrorInvalidValue;")
-                    L.append(f"        hipLaunchKernelGGL(({kname}<R, false, true>), dim3((unsigned)((n_evt + 63) / 64)), dim3(64 * n_good), 0, st, "
-                             "mom, n_evt, ld, hel, n_good, mt, gs, jamp, nullptr, nullptr, *fc);")
-                    L.append("        return hipGetLastError();")
+                    if self.name in HEL_SUM_IN_KERNEL:
+                        L.append("        if (n_good > 16) return hipErrorInvalidValue;")
+                        L.append(f"        hipLaunchKernelGGL(({kname}<R, false, true>), dim3((unsigned)((n_evt + 63) / 64)), dim3(64 * n_good), 0, st, "
+                                 "mom, n_evt, ld, hel, n_good, mt, gs, jamp, nullptr, nullptr, *fc);")
+                        L.append("        return hipGetLastError();")
+                    else:
+                        L.append("        return hipErrorInvalidValue;  // below the lane kernel's batch size: no such kernel")
                     L.append("    }")
                 L.append("    if (chan)")
                 tail = ", none" if fused else ""
@@ -907,7 +910,7 @@ class Process:
                  f"{n_order},")
         L.append(f"        {self.n_diagrams}, {self.n_amplitudes}, {fl}.0, {self.flops_exec}.0, proc_{nm}::NSLOT,")
         L.append(f"        proc_{nm}::diagram_lines, {nlines}, {0 if self.lines is None else 1}, {1 if fused else 0}, "
-                 f"{1 if fused and nm in HEL_SUM_IN_KERNEL else 0},")
+                 f"{1 if fused and nm in HEL_SUM_IN_KERNEL else 0}, {LANE_MIN_EVENTS if fused and nm in LANE_PER_EVENT else 0},")
         L.append(f"        proc_{nm}::launch<double>, proc_{nm}::launch<float>,")
         L.append("    };")
         L.append("    return &d;")
@@ -1141,13 +1144,13 @@ class Process:
         for each good helicity the diagram program, the colour sum (one flow; in the mixed forms
         the scalar equivalent of the 16-bit tile) and the helicity sum in the groups and order of
         the separate helicity-sum kernel, so the result is bitwise that of the other paths."""
-        if self.nc != 1:
-            raise ValueError("the lane-per-event kernel handles one colour flow")
+        if self.nc > 6:
+            raise ValueError("the lane-per-event kernel sums at most six colour flows in registers")
         L = []
         L.append("template <class R>")
         L.append(f"__global__ __launch_bounds__(64, sizeof(R) == 8 ? {LANE_MIN_WAVES[0]} : {LANE_MIN_WAVES[1]}) void amp_lanes("
                  "const double* __restrict__ mom, int64_t n_evt, "
-                 "const signed char* __restrict__ hel, int n_good, double gs, FusedColour fc)")
+                 "const signed char* __restrict__ hel, int n_good, double mt, double gs, FusedColour fc)")
         L.append("{")
         L.append("    __shared__ double lds[4 * NPAR * 64];")
         L.append("    const int lane = threadIdx.x;")
@@ -1161,15 +1164,17 @@ class Process:
         L.append("#define JADD(s, ri, v) (Jr[2 * (s) + (ri)] += (v))")
         if LANE_HOIST_EXT:
             # each external state for both helicities, once per event; the loop selects
-            ext = re.compile(r"^\s*const W4<R> (w\d+) = (ext_\w+<R>)\((PM\(\d+\)), ([^,]+), lam\[(\d+)\]\);$")
+            ext = re.compile(r"^\s*const W4<R> (w\d+) = (ext_\w+<R>\(.*lam\[(\d+)\].*\));$")
             kept = []
             for ln in body:
                 m = ext.match(ln)
                 if not m:
                     kept.append(ln)
                     continue
-                w, fn, pm, mass, i = m.groups()
-                L.append(f"    const W4<R> {w}_p = {fn}({pm}, {mass}, 1), {w}_m = {fn}({pm}, {mass}, -1);")
+                w, call, i = m.groups()
+                call = re.sub(r"\bm\d+_(\d+)\b", r"PM(\1)", call)   # momenta read before the loop
+                plus, minus = (call.replace(f"lam[{i}]", v) for v in ("1", "-1"))
+                L.append(f"    const W4<R> {w}_p = {plus}, {w}_m = {minus};")
                 kept.append(f"    const W4<R> {w} = lam[{i}] > 0 ? {w}_p : {w}_m;")
             body = kept
         L.append("    double s = 0.0, m = 0.0;")
@@ -1179,16 +1184,19 @@ class Process:
         L.append("        int lam[NPAR];")
         L.append("#pragma unroll")
         L.append("        for (int i = 0; i < NPAR; ++i) lam[i] = hel[h * NPAR + i];")
-        L.append("        R Jr[2] = {(R)0, (R)0};")
-        L.append("        cx<R> a;")
+        L.append("        R Jr[2 * NC] = {};")
+        L.append("        cx<R> a, sa;")
         L += ["    " + ln for ln in body]
-        L.append("        asm volatile(\"\" : \"+v\"(Jr[0]), \"+v\"(Jr[1]));  // the jamp as the other paths store it")
+        L.append("#pragma unroll")
+        L.append("        for (int k = 0; k < 2 * NC; ++k) asm volatile(\"\" : \"+v\"(Jr[k]));  // the jamps as the other paths hold them")
         L.append("        if constexpr (sizeof(R) == 8)")
-        L.append("            m += cs1(Jr[0], Jr[1], static_cast<const double*>(fc.aop)[0]);")
-        L.append("        else if (fc.form == ME_MIXED_BF16)")
-        L.append("            m += cs1_h16<Bf16Terms>(Jr[0], Jr[1], static_cast<const __bf16*>(fc.aop));")
-        L.append("        else")
-        L.append("            m += cs1_h16<Fp16Terms>(Jr[0], Jr[1], static_cast<const _Float16*>(fc.aop));")
+        L.append("            m += colour_sum_regs<NC>(Jr, static_cast<const double*>(fc.aop));")
+        L.append("        else if constexpr (NC == 1) {  // the 16-bit forms: one flow only")
+        L.append("            if (fc.form == ME_MIXED_BF16)")
+        L.append("                m += cs1_h16<Bf16Terms>(Jr[0], Jr[1], static_cast<const __bf16*>(fc.aop));")
+        L.append("            else")
+        L.append("                m += cs1_h16<Fp16Terms>(Jr[0], Jr[1], static_cast<const _Float16*>(fc.aop));")
+        L.append("        }")
         L.append("        if (++in_group == fc.hel_per_group || h + 1 == n_good) {")
         L.append("            s += m;")
         L.append("            m = 0.0;")

@@ -131,7 +131,8 @@ def expand_sums(text):
 @pytest.mark.parametrize("name", ["gg_tt", "gg_ttg", "gg_ttgg"])
 def test_every_diagram_evaluated_once(name):
     P = emit.Process(name)
-    src = P.source()
+    # the helicity-wave kernel (the one-lane-per-event kernel after it repeats the program)
+    src = P.source().split("void amp_lanes(")[0]
     # one vertex line per group of entries that differ in one operand (the vertex on the sum of
     # those operands), each entry in exactly one group
     lines = re.findall(r"^\s+a = amp_(.*)$", expand_sums(src), re.M)

@@ -271,13 +271,14 @@ def test_fused_colour_sum_equals_separate_kernel(name, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed_fp16", "mixed_bf16"])
-@pytest.mark.parametrize("name", ["ee_mumu", "ee_mumu_z"])
+@pytest.mark.parametrize("name", ["ee_mumu", "ee_mumu_z", "gg_tt"])
 def test_lane_per_event_kernel(name, precision):
-    """e+e- batches of 2^16 events or more take the kernel with one lane per event (all good
-    helicities in turn; in the mixed forms the scalar equivalent of the one-flow 16-bit tile);
-    its results are bitwise those of the helicity-wave kernel (the same events in batches below
-    2^16) and of the separate colour-sum path, and the oracle's within the FP64 bar, or the
-    mixed forms' (every event, ragged tail)"""
+    """e+e- and gg->tt~ batches of 2^16 events or more take the kernel with one lane per event
+    (all good helicities in turn; in the mixed forms of one flow the scalar equivalent of the
+    16-bit tile; gg->tt~'s mixed forms keep the helicity waves); its results are bitwise those of
+    the helicity-wave kernel (the same events in batches below 2^16) and of the separate
+    colour-sum path, and the oracle's within the FP64 bar, or the mixed forms' (every event,
+    ragged tail)"""
     n = (1 << 16) + 4099
     print(f"case lane per event {name} {precision} n={n}", flush=True)
     p = oracle.rambo(17, W.sqrt_s(name), W.final_masses(name), n)

@@ -490,7 +490,7 @@ def _node_tree(P, key):
     return ({"U": "fstr_u", "V": "fstr_v", "JF": "jf"}[kind],) + deps
 
 
-@pytest.mark.parametrize("name", ["gg_ttgg", "gg_ttggg"])
+@pytest.mark.parametrize("name", ["gg_tt", "gg_ttg", "gg_ttgg", "gg_ttggg"])
 def test_emitted_vertices_on_sums_equal_the_diagram_amplitudes(name):
     """expand every `a = amp_...` line of the emitted kernels symbolically (operand sums distributed
     through the vertices): it equals the sum of its diagram amplitudes, each with its unit factor,

@@ -191,7 +191,7 @@ __device__ __forceinline__ double colour_sum_regs(const double* Jr, const double
 // D * |M_h|^2 for event column i (the four lane groups' shares add up to it).  load(c, ri) gives
 // the jamp of colour c (re/im) of this lane's column.  A: the tile operands in registers when
 // AREG, else read from aop.
-template <int NC, bool AREG, class Load>
+template <int NC, bool AREG, class Load, bool ALDS = false>
 __device__ __forceinline__ double cs64_column(const Load& load, const double* A, const double* aop, int lane)
 {
     if constexpr (NC == 1) {
@@ -222,7 +222,9 @@ __device__ __forceinline__ double cs64_column(const Load& load, const double* A,
         int q = 0;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-            const double* ap = opaque(aop);
+            // operands from LDS (ALDS): read tile row by tile row, not all at once
+            if constexpr (ALDS) __asm__ volatile("" ::: "memory");
+            const double* ap = ALDS ? aop : opaque(aop);
             v4d d = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int kt = 4 * mt; kt < KT; ++kt, ++q) {
@@ -237,6 +239,9 @@ __device__ __forceinline__ double cs64_column(const Load& load, const double* A,
     return part_h;
 }
 
+#ifndef CS64_A_IN_LDS
+#define CS64_A_IN_LDS 1
+#endif
 // A operands, per lane, in the kernel's tile order (mt ascending, then kt >= 4 mt):
 // aop[q * 64 + l] = A[16 mt + l % 16][4 kt + l / 16].
 template <int NC>
@@ -248,6 +253,14 @@ __global__ __launch_bounds__(256) void colour_sum_f64(const double* __restrict__
 {
     constexpr int NT = cs64_tiles(NC);
     constexpr bool AREG = NT <= 24;
+    // the large matrix: its operands staged in LDS once per workgroup (NT * 512 B), instead of
+    // each wave reading them through the caches for every tile
+    constexpr bool ALDS = !AREG && CS64_A_IN_LDS;
+    __shared__ double As[ALDS ? NT * 64 : 1];
+    if constexpr (ALDS) {
+        for (int k = threadIdx.x; k < NT * 64; k += 256) As[k] = aop[k];
+        __syncthreads();
+    }
     const int lane = threadIdx.x & 63;
     const int64_t e0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
     if (e0 >= n_evt) return;
@@ -265,7 +278,7 @@ __global__ __launch_bounds__(256) void colour_sum_f64(const double* __restrict__
     for (int h = h0; h < h1; ++h) {
         const double* Jh = J + (int64_t)h * (2 * NC) * ld;
         const auto load = [&](int c, int ri) { return Jh[(int64_t)(2 * c + ri) * ld + ec]; };
-        double part_h = sum_lane_groups(cs64_column<NC, AREG>(load, A, aop, lane));
+        double part_h = sum_lane_groups(cs64_column<NC, AREG, decltype(load), ALDS>(load, A, ALDS ? As : aop, lane));
         if (out_hel && g == 0 && valid) out_hel[e * n_good + h] = part_h * scale_hel;
         me += part_h;
     }

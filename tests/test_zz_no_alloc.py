@@ -11,6 +11,7 @@ from tests import workloads as W
 CASES = [
     ("gg_ttgg", "fp64", 100003, 1000),
     ("gg_tt", "mixed_fp16", (1 << 19) + 17, 3000),
+    ("gg_tt", "fp64", (1 << 19) + 17, 70001),
     ("gg_ttggg", "fp64", 200, 70),
     ("gg_ttggg", "mixed_bf16", 300, 100),
     ("ee_mumu", "fp64", 8197, 64),
